@@ -1,0 +1,394 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-derives an oracle function by retyping it: each checks a
+closed form, a library routine, a brute-force enumeration, a property that
+must hold, a value printed in the paper, or a published test vector.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1908_02461_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _crand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- draws ----
+
+def test_splitmix64_published_vectors(orc):
+    for idx, hexval in _golden_rows("splitmix64_seed0.txt"):
+        assert orc.splitmix64_at(0, int(idx)) == int(hexval, 16)
+
+
+def test_inverse_mod_brute_force(orc):
+    for n in (2, 16, 64, 1024):
+        for a in range(1, n, 2):
+            inv = orc.inverse_mod(a, n)
+            assert 0 <= inv < n and (a * inv) % n == 1
+    assert orc.inverse_mod(6, 16) == -1
+
+
+def test_draw_is_an_invertible_permutation(orc):
+    for n in (16, 1 << 14, 1 << 22):
+        for it in range(20):
+            s, t, si = orc.draw(1234, 3, 1, it, 0, n)
+            assert s % 2 == 1 and 0 < s < n and 0 <= t < n
+            assert (s * si) % n == 1
+    # distinct keys give distinct words
+    words = {orc.draw_word(7, sig, ph, it, ax) for sig in range(3) for ph in range(3)
+             for it in range(5) for ax in range(2)}
+    assert len(words) == 3 * 3 * 5 * 2
+
+
+# ------------------------------------------------------------------ DFT ----
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 32, 256])
+def test_naive_dft_matches_numpy(orc, n):
+    rng = np.random.default_rng(n)
+    x = _crand(rng, n)
+    X = orc.dft_naive(x)
+    ref = np.fft.fft(x)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [2, 16, 512, 4096])
+def test_fft_matches_naive_and_numpy(orc, n):
+    rng = np.random.default_rng(n + 1)
+    x = _crand(rng, n)
+    X = orc.fft(x)
+    ref = np.fft.fft(x)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(X - ref)) <= 1e-13 * scale * np.log2(n + 1)
+    if n <= 512:
+        assert np.max(np.abs(X - orc.dft_naive(x))) <= 1e-12 * scale
+
+
+def test_fft_closed_forms(orc):
+    n = 1024
+    rng = np.random.default_rng(5)
+    x = _crand(rng, n)
+    X = orc.fft(x)
+    # Parseval for the unnormalised DFT
+    assert np.isclose(np.sum(np.abs(X) ** 2), n * np.sum(np.abs(x) ** 2), rtol=1e-12)
+    # an impulse at 0 is a constant spectrum
+    d = np.zeros(n, complex)
+    d[0] = 2.5
+    assert np.allclose(orc.fft(d), 2.5, atol=1e-13)
+    # a tone e^{+2 pi i f0 u/n} is n times a delta at f0 (omega = e^{-2 pi i/n})
+    f0 = 37
+    tone = np.exp(2j * np.pi * f0 * np.arange(n) / n)
+    T = orc.fft(tone)
+    expect = np.zeros(n, complex)
+    expect[f0] = n
+    assert np.max(np.abs(T - expect)) <= 1e-9
+    # the inverse recovers the input
+    assert np.allclose(orc.idft_naive(orc.dft_naive(x[:64])), x[:64], atol=1e-12)
+
+
+def test_fft2_matches_numpy(orc):
+    rng = np.random.default_rng(9)
+    x = _crand(rng, 64, 64)
+    assert np.max(np.abs(orc.fft2(x) - np.fft.fft2(x))) <= 1e-11
+
+
+# -------------------------------------------------------------- Lemma 1 ----
+
+def test_lemma1_permutation_brute_force(orc):
+    """Lemma 1: the DFT of x_{sigma t + tau} at sigma i is x_hat_i omega^{-tau i}."""
+    n = 16
+    rng = np.random.default_rng(11)
+    x = _crand(rng, n)
+    X = orc.dft_naive(x)
+    w = np.exp(-2j * np.pi / n)
+    u = np.arange(n)
+    for sigma in range(1, n, 2):
+        for tau in range(n):
+            PX = orc.dft_naive(x[(sigma * u + tau) % n])
+            lhs = PX[(sigma * u) % n]
+            rhs = X * w ** (-(tau * u % n))
+            assert np.max(np.abs(lhs - rhs)) < 1e-11
+
+
+# -------------------------------------------------------------- Lemma 2 ----
+
+def test_lemma2_fold_of_full_signal(orc):
+    """Lemma 2 (ranges u in [n/B], i in [B]): folding gives x_hat at multiples of n/B."""
+    n, B = 1024, 32
+    rng = np.random.default_rng(13)
+    x = _crand(rng, n)
+    X = np.fft.fft(x)
+    ones = np.ones(n)
+    yhat = orc.hash_1d(x, 1, 0, B, n, ones)
+    assert np.max(np.abs(yhat - X[:: n // B])) < 1e-10
+    # with a permutation the fold samples the permuted spectrum (Lemma 1 + 2)
+    sigma, tau = 77, 301
+    si = orc.inverse_mod(sigma, n)
+    yhat = orc.hash_1d(x, sigma, tau, B, n, ones)
+    j = np.arange(B)
+    f = (si * j * (n // B)) % n
+    expect = X[f] * np.exp(2j * np.pi * ((tau * f) % n) / n)
+    assert np.max(np.abs(yhat - expect)) < 1e-10
+
+
+def test_lemma2_fold_2d(orc):
+    N, B = 64, 8
+    rng = np.random.default_rng(17)
+    x = _crand(rng, N, N)
+    X = np.fft.fft2(x)
+    yhat = orc.hash_2d(x, [1, 1], [0, 0], B, N, np.ones(N))
+    assert np.max(np.abs(yhat - X[:: N // B, :: N // B])) < 1e-9
+
+
+# --------------------------------------------------------------- window ----
+
+def _analytic_window_hat(n, B, w, delta, q):
+    """Gaussian (continuous transform) convolved with the one-bucket box car."""
+    s = (w / 2.0) / np.sqrt(2.0 * np.log(1.0 / delta))
+    c = n // (2 * B)
+    o = np.arange(-c, c + 1)
+    u = q - o
+    return float(np.sum(s * np.sqrt(2 * np.pi) / n * np.exp(-2 * np.pi ** 2 * s ** 2 * u ** 2 / n ** 2)))
+
+
+@pytest.mark.parametrize("n,B,alpha,delta", [(1 << 14, 256, 32, 1e-8), (1 << 16, 1024, 16, 1e-6),
+                                             (4096, 64, 8, 1e-8)])
+def test_window_flat_gaussian(orc, n, B, alpha, delta):
+    w = orc.window_len(n, B, alpha)
+    G = orc.window_taps(n, B, w, delta)
+    # symmetric taps: G_{-w/2} = 0 and G_t = G_{-t}
+    assert G[0] == 0.0
+    assert np.allclose(G[1:], G[1:][::-1], rtol=0, atol=1e-12 * np.max(np.abs(G)))
+    c = n // (2 * B)
+    qs = list(range(-c, c + 1, max(1, c // 16))) + [c, 2 * c, 3 * c, n // B * 2]
+    # the literal sum agrees with the full length-n DFT of the zero-padded taps
+    t = np.arange(w) - w // 2
+    full = np.zeros(n)
+    full[t % n] = G
+    Ghat_fft = np.fft.fft(full) / n
+    for q in qs:
+        re, im = orc.window_hat(n, w, G, q, with_imag=True)
+        assert abs(im) < 1e-12
+        assert abs(re - Ghat_fft[q % n].real) < 1e-12
+        assert abs(re - _analytic_window_hat(n, B, w, delta, q)) < 20 * delta
+    # flat pass band and stop band
+    delta_w = (n / B) * 2 * np.log(1 / delta) / (np.pi * alpha)
+    for q in range(-c, c + 1):
+        g = orc.window_hat(n, w, G, q)
+        if abs(q) <= c - delta_w:
+            assert abs(g - 1.0) < 20 * delta
+        assert 0.45 < g < 1.0 + 20 * delta
+    for q in (int(np.ceil(c + delta_w)) + 1, n // B, 2 * n // B, 4 * n // B):
+        if q >= c + delta_w:
+            assert abs(orc.window_hat(n, w, G, q)) < 20 * delta
+
+
+# ----------------------------------------------------------------- hash ----
+
+def test_hash_partition_and_offsets(orc):
+    rng = np.random.default_rng(19)
+    for n, B in ((256, 16), (1024, 32), (64, 64)):
+        for _ in range(5):
+            sigma = int(rng.integers(0, n // 2)) * 2 + 1
+            si = orc.inverse_mod(sigma, n)
+            c, width = n // (2 * B), n // B
+            seen = np.zeros(n, int)
+            for j in range(B):
+                p = (j * width - c + np.arange(width)) % n
+                f = (si * p) % n
+                seen[f] += 1
+                for ff in f[:: max(1, width // 8)]:
+                    assert orc.hash_bucket(n, B, sigma, int(ff)) == j
+            assert np.all(seen == 1)
+            for f in range(0, n, max(1, n // 64)):
+                o = orc.hash_offset(n, B, sigma, f)
+                h = orc.hash_bucket(n, B, sigma, f)
+                assert -n / (2 * B) < o <= n / (2 * B)
+                assert (h * width - sigma * f - o) % n == 0
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_one_sparse_estimate_is_exact(orc, ndim):
+    """The estimator display is exact for one coefficient when G' comes from the taps."""
+    n = 1 << 14 if ndim == 1 else 256
+    B = 256 if ndim == 1 else 16
+    alpha = 32 if ndim == 1 else 8
+    for seed in range(5):
+        if ndim == 1:
+            x, locs, amps = synth.planted_1d(n, 1, seed, mag=("uniform", 0.3, 3.0))
+        else:
+            x, locs, amps = synth.planted_2d(n, 1, seed, mag=("uniform", 0.3, 3.0))
+        p = orc.Params.defaults(ndim, n, seed=100 + seed, fixed_B=B, fixed_k=1, alpha=alpha)
+        r = orc.atsfft(x, p)
+        assert locs[0] in r["locs"]
+        s = int(np.searchsorted(r["locs"], locs[0]))
+        est = r["est"][s]
+        assert np.max(np.abs(est - amps[0])) <= 1e-12 * abs(amps[0])
+        assert abs(r["vals"][s] - amps[0]) <= 1e-12 * abs(amps[0])
+
+
+# ------------------------------------------------------------ selection ----
+
+def test_rule_table(orc):
+    for kp, kc, dec in _golden_rows("brule_table.txt"):
+        assert orc.rule(int(kp), int(kc)) == int(dec), (kp, kc)
+
+
+def test_threshold_cases(orc):
+    m = np.zeros(64)
+    m[[3, 10]] = [4.0, 1.0]
+    assert orc.threshold(m) == pytest.approx(4e-6)
+    m = np.full(100, 2.0)
+    expect = max(np.log(100 / 0.01) * 2.0 / -np.log(0.9), 2e-6)
+    assert orc.threshold(m) == pytest.approx(expect, rel=1e-14)
+    # exponential noise: T sits near ln(count/rate) times the mean
+    rng = np.random.default_rng(23)
+    cnt = 1 << 16
+    m = rng.exponential(3.0, cnt)
+    T = orc.threshold(m)
+    assert 0.95 < T / (3.0 * np.log(cnt / 0.01)) < 1.05
+    assert np.sum(m > T) <= 3
+
+
+def test_local_max_hand_cases(orc):
+    m = np.array([0, 1, 0, 2, 0, 0, 3, 3], float)
+    assert orc.local_max_1d(m, 0.5) == 3
+    assert orc.local_max_1d(m, 2.5) == 1
+    assert orc.local_max_1d(np.zeros(8), 0.0) == 0
+    # a plateau gives one maximum; the ring wraps
+    m = np.array([5, 0, 0, 0, 0, 0, 0, 5], float)
+    assert orc.local_max_1d(m, 1.0) == 1
+    m2 = np.zeros((8, 8))
+    m2[0, 0] = 3.0
+    m2[7, 7] = 2.0  # diagonal neighbour through the wrap
+    m2[4, 4] = 1.0
+    m2[4, 5] = 1.0
+    assert orc.local_max_2d(m2, 0.5) == 2
+    m2[2, 6] = 9.0
+    assert orc.local_max_2d(m2, 0.5) == 3
+
+
+def test_paper_two_spike_example(orc):
+    """Sec. III-A: k = 2 in 2^11 x 2^11 hashed into 2^6 x 2^6 bins gives 2 maxima."""
+    (N, B, k, expect), = [tuple(int(v) for v in r) for r in _golden_rows("paper_example_2d.txt")]
+    x, _, _ = synth.planted_2d(N, k, seed=2019)
+    w = orc.window_len(N, B, 16)
+    G = orc.window_taps(N, B, w, 1e-8)
+    s0, t0, _ = orc.draw(5, 0, 0, 0, 0, N)
+    s1, t1, _ = orc.draw(5, 0, 0, 0, 1, N)
+    yhat = orc.hash_2d(x, [s0, s1], [t0, t1], B, w, G)
+    m = np.abs(yhat) ** 2
+    T = orc.threshold(m)
+    assert orc.local_max_2d(m, T) == expect
+
+
+def test_topnum_property(orc):
+    rng = np.random.default_rng(29)
+    for _ in range(50):
+        B = int(rng.integers(4, 40))
+        m = rng.integers(0, 6, B).astype(float)  # many ties
+        T = 0.5
+        num = int(rng.integers(1, B + 2))
+        J, c = orc.topnum(m, T, num)
+        sig = m > T
+        assert c == min(num, int(sig.sum())) == int(J.sum())
+        assert np.all(sig[J])
+        for a in np.flatnonzero(J):
+            for b in np.flatnonzero(sig & ~J):
+                assert m[a] > m[b] or (m[a] == m[b] and a < b)
+
+
+@pytest.mark.parametrize("ndim,n,B", [(1, 1024, 32), (1, 4096, 256), (2, 64, 8)])
+def test_vote_histogram_vs_forward_hash(orc, ndim, n, B):
+    rng = np.random.default_rng(31 + n)
+    L = 5
+    cnt = B if ndim == 1 else B * B
+    sig = rng.integers(0, n // 2, size=(L, ndim)) * 2 + 1
+    sinv = np.array([[orc.inverse_mod(int(s), n) for s in row] for row in sig])
+    J = rng.random((L, cnt)) < 0.2
+    votes = orc.vote_hist(ndim, n, B, sinv if ndim == 2 else sinv[:, 0], J)
+    c, width = n // (2 * B), n // B
+    f = np.arange(n)
+    expect = np.zeros(n if ndim == 1 else n * n, int)
+    for l in range(L):
+        h = [(((sig[l, a] * f) % n + c) % n) // width for a in range(ndim)]
+        if ndim == 1:
+            expect += J[l][h[0]]
+        else:
+            expect += J[l][(h[0][:, None] * B + h[1][None, :]).ravel()]
+    assert np.array_equal(votes, expect)
+
+
+def test_median_vs_sort(orc):
+    rng = np.random.default_rng(37)
+    for L in (1, 3, 5, 9, 31):
+        for _ in range(20):
+            v = rng.standard_normal(L)
+            assert orc.median(v) == np.median(v)
+
+
+def test_l1_error_hand_cases(orc):
+    Xt = np.array([1, 0, 0, 2j, 0, 0.5], complex)
+    assert orc.l1_error(Xt, [0, 3, 5], [1, 2j, 0.5], 3) == 0.0
+    assert orc.l1_error(Xt, [0, 3], [1, 2j], 3) == pytest.approx(0.5 / 3)
+    assert orc.l1_error(Xt, [0, 1, 3, 5], [1.5, 1j, 2j, 0.5], 2) == pytest.approx((0.5 + 1.0) / 2)
+    assert orc.l1_error(Xt, [], [], 1) == pytest.approx(3.5)
+
+
+# ------------------------------------------------------------ end to end ----
+
+def test_planted_noiseless_recovery_1d(orc):
+    """Small 1D workload (n = 2^14, k = 8, |a| = 1, no noise): exact recovery, 100 seeds."""
+    n, k = 1 << 14, 8
+    for seed in range(100):
+        x, locs, amps = synth.planted_1d(n, k, seed)
+        r = orc.atsfft(x, orc.Params.defaults(1, n, seed=seed), trace=False)
+        assert r["status"] & orc.EMPTY == 0
+        idx = np.searchsorted(r["locs"], locs)
+        assert np.all(idx < len(r["locs"])) and np.array_equal(r["locs"][idx], locs), seed
+        assert np.max(np.abs(r["vals"][idx] - amps)) < 1e-9, seed
+        # anything else located is leakage-sized
+        others = np.setdiff1d(np.arange(len(r["locs"])), idx)
+        assert np.all(np.abs(r["vals"][others]) < 1e-6)
+
+
+def test_planted_noiseless_recovery_2d(orc):
+    N, k = 512, 8
+    for seed in range(6):
+        x, locs, amps = synth.planted_2d(N, k, seed)
+        p = orc.Params.defaults(2, N, seed=seed, alpha=8, alpha_probe=4, B_max=64)
+        r = orc.atsfft(x, p, trace=False)
+        idx = np.searchsorted(r["locs"], locs)
+        assert np.all(idx < len(r["locs"])) and np.array_equal(r["locs"][idx], locs), seed
+        assert np.max(np.abs(r["vals"][idx] - amps)) < 1e-3, seed
+
+
+def test_zero_signal_is_empty(orc):
+    r = orc.atsfft(np.zeros(4096, complex), orc.Params.defaults(1, 4096))
+    assert r["status"] & orc.EMPTY and r["count"] == 0 and r["khat"] == 0
+    assert r["status"] & orc.PROBE_SATURATED
+
+
+def test_parameter_validation(orc):
+    x = np.zeros(1024, complex)
+    for bad in (dict(n=1000), dict(L_est=8), dict(T_vote=0), dict(T_vote=10), dict(B0=48),
+                dict(B0=64, B_max=32), dict(delta=0.0)):
+        p = orc.Params.defaults(1, 1024)
+        for k, v in bad.items():
+            setattr(p, k, v)
+        with pytest.raises(ValueError):
+            orc.atsfft(x if p.n == 1024 else np.zeros(p.n, complex), p)
