@@ -1,0 +1,210 @@
+/*
+ * atsfft.h - C ABI of an MI355X (gfx950) implementation of ATSFFT, the
+ * adaptive-tuning sparse FFT of Shi, Yang, Zhang and You, "ATSFFT: A Novel
+ * Sparse Fast Fourier Transform Enabled With Sparsity Detection"
+ * (arXiv:1908.02461).
+ *
+ * The library takes a signal (1D, length n) or an image (2D, N x N) whose
+ * spectrum is sparse, probes the unknown sparsity k with the paper's
+ * adaptive bucket-count iteration (Sec. III-A, Algorithm 2), locates the
+ * significant frequencies by voting over randomly permuted, windowed and
+ * folded copies of the input (Sec. II-A and II-B, Algorithm 1), and
+ * estimates their coefficients as the median over several estimation loops
+ * (the estimator display of Sec. II-B).  The output is the k-sparse
+ * approximation x' of the unnormalised DFT, x_hat_f = sum_u x_u omega^{f u},
+ * omega = e^{-2 pi i / n} (the DFT display of Sec. II): ascending frequency
+ * indices (1D: f; 2D: f1 * N + f2) and their complex values.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (HIP global memory); all other
+ *     pointers are host pointers.
+ *   - Complex arrays are interleaved (re, im) in the plan's precision:
+ *     ATSFFT_C64 = two floats, ATSFFT_C128 = two doubles.
+ *   - 2D images are row-major, x[u * N + v].
+ *   - The caller owns every buffer it passes in; the plan owns its window
+ *     tables (device memory it allocates and atsfft_destroy frees).
+ *   - Execution entry points only enqueue work on `stream` and return; their
+ *     return code reports argument and launch errors.  Per-signal outcomes
+ *     are the ATSFFT_SIG_* bits written to sig_status_dev.
+ *   - No entry point aborts, exits or throws.  A plan may be used by one
+ *     stream at a time.
+ */
+#ifndef ATSFFT_H
+#define ATSFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum atsfft_status {
+  ATSFFT_SUCCESS = 0,
+  ATSFFT_EINVAL = 1,        /* invalid descriptor, plan or argument */
+  ATSFFT_ENODEVICE = 2,     /* no usable gfx950 device */
+  ATSFFT_ENOMEM = 3,        /* device allocation failed */
+  ATSFFT_ELAUNCH = 4,       /* a kernel launch or HIP call failed */
+  ATSFFT_ENOTSUPPORTED = 5  /* valid request this build does not provide */
+} atsfft_status;
+
+enum { ATSFFT_C64 = 0, ATSFFT_C128 = 1 };
+
+/* Per-signal outcome bits (sig_status_dev). */
+enum {
+  ATSFFT_SIG_OK = 0,
+  ATSFFT_SIG_TRUNCATED = 1,           /* |S| > max_out: count holds |S|, locs/vals unwritten */
+  ATSFFT_SIG_PROBE_NOT_CONVERGED = 2, /* the probe hit its iteration limit */
+  ATSFFT_SIG_PROBE_SATURATED = 4,     /* the probe wanted a bucket count above B_max */
+  ATSFFT_SIG_EMPTY = 8                /* the probed sparsity is 0: nothing located */
+};
+
+/* Descriptor flags. */
+enum {
+  ATSFFT_FLAG_FIXED_B = 1 /* skip the probe: bucket count fixed_B, khat = fixed_k (Algorithm 1) */
+};
+
+/*
+ * Plan descriptor.  atsfft_default_desc fills every knob; fields set to the
+ * defaults reproduce the readings documented with the library.
+ *
+ *   ndim, n      1 (length n) or 2 (N x N image, n = N); n a power of two,
+ *                1D: 2^6 <= n <= 2^30; 2D: 2^4 <= N <= 2^15.
+ *   dtype        ATSFFT_C64 or ATSFFT_C128 (input, values and arithmetic).
+ *   max_out      capacity of locs/vals per signal, 1 <= max_out <= 16384.
+ *   seed         key of the counter-based SplitMix64 draws of (sigma, tau).
+ *   B0, B_max    first and largest bucket count per axis (powers of two);
+ *                B_max^ndim complex values must fit the device's LDS twice.
+ *   alpha_probe, alpha   window length factors (w = alpha * B, capped at n),
+ *                even, >= 2.
+ *   L_loc, L_est location and estimation loop counts (L_est odd, <= 31;
+ *                L_loc <= 31); T_vote in [1, L_loc] is the vote threshold.
+ *   P_max        probe iteration limit (<= 32).
+ *   d            cutoff multiplier: each location loop keeps the d * khat
+ *                strongest significant buckets.
+ *   gamma        occupancy guard of the probe: a local-maximum count k is
+ *                acted on only once B^ndim >= gamma * k (0 disables it).
+ *   delta        window leakage (the Gaussian's value at the window edge).
+ *   q, noise_rate, rho   significance threshold: noise floor from the
+ *                q-quantile of |y_hat|^2, c_noise = ln(B^ndim / noise_rate),
+ *                and a relative floor rho * max |y_hat|^2.
+ *   fixed_B, fixed_k     used with ATSFFT_FLAG_FIXED_B.
+ *   max_batch    largest batch passed to atsfft_execute_batched.
+ */
+typedef struct atsfft_desc {
+  int32_t ndim;
+  int32_t dtype;
+  int64_t n;
+  int64_t max_out;
+  uint64_t seed;
+  uint32_t flags;
+  int32_t max_batch;
+  int64_t B0;
+  int64_t B_max;
+  int32_t alpha_probe;
+  int32_t alpha;
+  int32_t L_loc;
+  int32_t L_est;
+  int32_t T_vote;
+  int32_t P_max;
+  int32_t d;
+  int32_t gamma;
+  double delta;
+  double q;
+  double noise_rate;
+  double rho;
+  int64_t fixed_B;
+  int64_t fixed_k;
+} atsfft_desc;
+
+typedef struct atsfft_plan_s *atsfft_plan_t;
+
+/* Fill *d with the defaults for (ndim, n, dtype).  Host only, no device use. */
+atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32_t dtype);
+
+/*
+ * Create a plan on the current HIP device: validates *d synchronously,
+ * builds the window tables of every bucket count the probe may visit (the
+ * flat window of Sec. II-A-2 generated in FP64, stored in the plan's
+ * precision) and keeps them until atsfft_destroy.  On error *out is NULL.
+ * Errors: ATSFFT_EINVAL, ATSFFT_ENODEVICE, ATSFFT_ENOMEM, ATSFFT_ELAUNCH.
+ */
+atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d);
+
+/* Bytes of device workspace atsfft_execute_batched needs for `batch` signals. */
+atsfft_status atsfft_workspace_size(atsfft_plan_t plan, int32_t batch, size_t *bytes);
+
+/*
+ * Algorithm 2 on `batch` signals of the plan's size, stored back to back in
+ * x_dev ([batch][n] or [batch][N][N]).  Outputs, all device memory:
+ *   locs_dev       int64 [batch][max_out], ascending located frequencies;
+ *   vals_dev       complex [batch][max_out], their estimated coefficients;
+ *   count_dev      int32 [batch], |S| (may exceed max_out: TRUNCATED);
+ *   khat_dev       int32 [batch], the probed sparsity;
+ *   sig_status_dev uint32 [batch], ATSFFT_SIG_* bits.
+ * Entries past count are left unwritten.  ws_dev must hold
+ * atsfft_workspace_size(plan, batch) bytes; its contents on entry do not
+ * matter and on return hold the trace read by atsfft_trace_read.
+ * Errors: ATSFFT_EINVAL (null pointer, batch outside [1, max_batch], ws too
+ * small), ATSFFT_ELAUNCH.
+ */
+atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const void *x_dev,
+                                     int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
+                                     int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev,
+                                     size_t ws_bytes, hipStream_t stream);
+
+/* atsfft_execute_batched with batch = 1. */
+atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *locs_dev,
+                             void *vals_dev, int32_t *count_dev, int32_t *khat_dev,
+                             uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes,
+                             hipStream_t stream);
+
+/*
+ * Gradient of a real loss through the value estimates at fixed located
+ * frequencies and median choices.  Not provided by this build: returns
+ * ATSFFT_ENOTSUPPORTED after validating its arguments.
+ */
+atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *grad_vals_dev,
+                              const void *ws_dev, void *grad_x_dev, hipStream_t stream);
+
+/*
+ * Debug trace of one signal of the last execute that used ws_dev, copied to
+ * host memory after synchronising `stream`.  Fills the scalar fields and,
+ * when non-NULL, the arrays (sizes from the plan: Bc = B_max^ndim):
+ *   probe_B/probe_k/probe_dec  int32 [P_max], probe_T double [P_max];
+ *   T_loc double [L_loc], J_count int32 [L_loc];
+ *   yhat   complex (plan precision) [L_loc + L_est][Bc] (bucket DFTs at B_star);
+ *   J_bits uint32 [L_loc][Bc / 32] (bit b of loop l: bucket b selected).
+ */
+typedef struct atsfft_trace {
+  int32_t B_star, khat, n_probe, count;
+  uint32_t status;
+  int32_t *probe_B, *probe_k, *probe_dec;
+  double *probe_T;
+  double *T_loc;
+  int32_t *J_count;
+  void *yhat;
+  uint32_t *J_bits;
+} atsfft_trace;
+
+atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t signal,
+                                atsfft_trace *out, hipStream_t stream);
+
+/* Release the plan's device tables.  Null is accepted. */
+atsfft_status atsfft_destroy(atsfft_plan_t plan);
+
+/* Static description of a status code. */
+const char *atsfft_status_string(atsfft_status s);
+
+/* Library version string. */
+const char *atsfft_version(void);
+
+/* Last error message recorded on this thread (static storage, never null). */
+const char *atsfft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

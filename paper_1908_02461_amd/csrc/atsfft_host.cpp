@@ -1,0 +1,476 @@
+// Host side of the ATSFFT C ABI: descriptor defaults and validation, the
+// plan's window tables, workspace layout and the execute entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "atsfft.h"
+#include "atsfft_internal.h"
+
+using namespace atsfft;
+
+struct atsfft_plan_s {
+  atsfft_desc d;
+  int device;
+  uint32_t logn;
+  uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
+  void *G_dev;       // taps, plan precision
+  void *Ghat_dev;    // G'(o) tables, plan precision
+  int64_t *tab_dev;  // [96] element offsets by log2 B
+  size_t bucket_smem, est_smem;
+};
+
+namespace {
+
+thread_local std::string g_err = "";
+
+atsfft_status fail(atsfft_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+uint32_t ilog2_host(uint64_t v) {
+  uint32_t r = 0;
+  while ((uint64_t)1 << (r + 1) <= v) ++r;
+  return r;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// The flat window of Sec. II-A-2, read as a Gaussian in time multiplied by
+// the time image of a one-bucket box car (a Dirichlet kernel over the n/B+1
+// bins |o| <= n/(2B)).  The Gaussian falls to delta at |t| = w/2; the tap at
+// t = -w/2 is zero so that the taps are symmetric.  out[t + w/2].
+void window_taps(int64_t n, int64_t B, int64_t w, double delta, std::vector<double> &out) {
+  out.assign((size_t)w, 0.0);
+  const int64_t half = w / 2;
+  const double ln_delta = std::log(delta);
+  const int64_t width = n / B + 1;
+  for (int64_t t = 0; t < half; ++t) {
+    const double u = (double)t / (double)half;
+    const double gauss = std::exp(ln_delta * u * u);
+    double dir;
+    if (t == 0) {
+      dir = (double)width;
+    } else {
+      const int64_t num = (width * t) % (2 * n);  // exact reduction of width * t modulo 2n
+      dir = std::sin(M_PI * (double)num / (double)n) / std::sin(M_PI * (double)t / (double)n);
+    }
+    const double v = gauss * dir;
+    out[(size_t)(half + t)] = v;
+    if (t > 0) out[(size_t)(half - t)] = v;
+  }
+}
+
+atsfft_status validate(const atsfft_desc *d) {
+  if (!d) return fail(ATSFFT_EINVAL, "null descriptor");
+  if (d->ndim != 1 && d->ndim != 2) return fail(ATSFFT_EINVAL, "ndim must be 1 or 2");
+  if (d->dtype != ATSFFT_C64 && d->dtype != ATSFFT_C128) return fail(ATSFFT_EINVAL, "bad dtype");
+  if (!is_pow2(d->n)) return fail(ATSFFT_EINVAL, "n must be a power of two");
+  if (d->ndim == 1 && (d->n < 64 || d->n > ((int64_t)1 << 30)))
+    return fail(ATSFFT_EINVAL, "1D n must be in [2^6, 2^30]");
+  if (d->ndim == 2 && (d->n < 16 || d->n > ((int64_t)1 << 15)))
+    return fail(ATSFFT_EINVAL, "2D N must be in [2^4, 2^15]");
+  if (d->max_out < 1 || d->max_out > kMaxOut) return fail(ATSFFT_EINVAL, "max_out must be in [1, 16384]");
+  if (d->max_batch < 1 || d->max_batch > 65535) return fail(ATSFFT_EINVAL, "max_batch must be in [1, 65535]");
+  const int64_t Bmin = d->ndim == 1 ? 2 : 4;
+  const bool fixed = (d->flags & ATSFFT_FLAG_FIXED_B) != 0;
+  if (fixed) {
+    if (!is_pow2(d->fixed_B) || d->fixed_B < Bmin || d->fixed_B > d->n / 2)
+      return fail(ATSFFT_EINVAL, "fixed_B must be a power of two in [2, n/2] (2D: [4, N/2])");
+    if (d->fixed_k < 0) return fail(ATSFFT_EINVAL, "fixed_k must be >= 0");
+  } else {
+    if (!is_pow2(d->B0) || !is_pow2(d->B_max) || d->B0 < Bmin || d->B0 > d->B_max || d->B_max > d->n / 2)
+      return fail(ATSFFT_EINVAL, "need B0 <= B_max, powers of two in [2, n/2] (2D: [4, N/2])");
+    if (d->alpha_probe < 2 || d->alpha_probe > 1024 || (d->alpha_probe & 1))
+      return fail(ATSFFT_EINVAL, "alpha_probe must be even in [2, 1024]");
+    if (d->P_max < 1 || d->P_max > kMaxProbe) return fail(ATSFFT_EINVAL, "P_max must be in [1, 32]");
+    if (d->gamma < 0) return fail(ATSFFT_EINVAL, "gamma must be >= 0");
+  }
+  const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
+  const int64_t Bc = d->ndim == 1 ? Bbig : Bbig * Bbig;
+  if (Bc > (int64_t)kBucketThreads * kBucketMaxPer)
+    return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384");
+  if (d->alpha < 2 || d->alpha > 1024 || (d->alpha & 1)) return fail(ATSFFT_EINVAL, "alpha must be even in [2, 1024]");
+  if (d->L_loc < 1 || d->L_loc > kMaxLoops - 1) return fail(ATSFFT_EINVAL, "L_loc must be in [1, 31]");
+  if (d->L_est < 1 || d->L_est > kMaxLoops - 1 || (d->L_est % 2) == 0)
+    return fail(ATSFFT_EINVAL, "L_est must be odd in [1, 31]");
+  if (d->T_vote < 1 || d->T_vote > d->L_loc) return fail(ATSFFT_EINVAL, "T_vote must be in [1, L_loc]");
+  if (d->d < 1 || d->d > 64) return fail(ATSFFT_EINVAL, "d must be in [1, 64]");
+  if (!(d->delta > 0.0 && d->delta < 1.0)) return fail(ATSFFT_EINVAL, "delta must be in (0, 1)");
+  if (!(d->q > 0.0 && d->q < 1.0)) return fail(ATSFFT_EINVAL, "q must be in (0, 1)");
+  if (!(d->noise_rate > 0.0)) return fail(ATSFFT_EINVAL, "noise_rate must be > 0");
+  if (!(d->rho >= 0.0)) return fail(ATSFFT_EINVAL, "rho must be >= 0");
+  return ATSFFT_SUCCESS;
+}
+
+Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
+  const atsfft_desc &d = p->d;
+  const size_t A = 256;
+  const size_t cs = d.dtype == ATSFFT_C64 ? 8 : 16;
+  const size_t Bc = p->Bc_max;
+  const size_t L = (size_t)(d.L_loc + d.L_est);
+  Layout l;
+  std::memset(&l, 0, sizeof(l));
+  size_t off = 0;
+  l.state = off;
+  off = align_up(off + sizeof(SigState), A);
+  l.hist = off;
+  off = align_up(off + (size_t)kMaxProbe * sizeof(ProbeRec), A);
+  l.tloc = off;
+  off = align_up(off + (size_t)kMaxLoops * 8, A);
+  l.jcount = off;
+  off = align_up(off + (size_t)kMaxLoops * 4, A);
+  l.yprobe = off;
+  off = align_up(off + Bc * cs, A);
+  l.ymain_loop = align_up(Bc * cs, A);
+  l.ymain = off;
+  off = align_up(off + L * l.ymain_loop, A);
+  l.jbits_loop = align_up(((Bc + 31) / 32) * 4, 16);
+  l.jbits = off;
+  off = align_up(off + (size_t)d.L_loc * l.jbits_loop, A);
+  l.jlist_loop = align_up(Bc * 4, 16);
+  l.jlist = off;
+  off = align_up(off + (size_t)d.L_loc * l.jlist_loop, A);
+  l.S = off;
+  off = align_up(off + (size_t)d.max_out * 4, A);
+  l.slice = off;
+  l.total = off * (size_t)batch;
+  return l;
+}
+
+template <typename T> std::vector<T> convert(const std::vector<double> &v) {
+  std::vector<T> out(v.size());
+  for (size_t i = 0; i < v.size(); ++i) out[i] = (T)v[i];
+  return out;
+}
+
+void free_plan(atsfft_plan_s *p) {
+  if (!p) return;
+  if (p->G_dev) (void)hipFree(p->G_dev);
+  if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
+  if (p->tab_dev) (void)hipFree(p->tab_dev);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *atsfft_version(void) { return "atsfft-mi355x 0.1.0 (gfx950)"; }
+
+const char *atsfft_last_error(void) { return g_err.c_str(); }
+
+const char *atsfft_status_string(atsfft_status s) {
+  switch (s) {
+    case ATSFFT_SUCCESS: return "success";
+    case ATSFFT_EINVAL: return "invalid argument";
+    case ATSFFT_ENODEVICE: return "no usable gfx950 device";
+    case ATSFFT_ENOMEM: return "device allocation failed";
+    case ATSFFT_ELAUNCH: return "kernel launch or HIP call failed";
+    case ATSFFT_ENOTSUPPORTED: return "not supported by this build";
+  }
+  return "unknown status";
+}
+
+atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32_t dtype) {
+  if (!d) return fail(ATSFFT_EINVAL, "null descriptor");
+  std::memset(d, 0, sizeof(*d));
+  d->ndim = ndim;
+  d->dtype = dtype;
+  d->n = n;
+  d->max_out = 4096;
+  d->seed = 0;
+  d->flags = 0;
+  d->max_batch = 1;
+  const bool c64 = dtype == ATSFFT_C64;
+  if (ndim == 2) {
+    d->alpha_probe = 4;
+    d->alpha = 8;
+    d->B0 = 8;
+    const int64_t cap = c64 ? 128 : 64;
+    d->B_max = n / d->alpha < cap ? n / d->alpha : cap;
+  } else {
+    d->alpha_probe = 16;
+    d->alpha = 32;
+    d->B0 = 32;
+    const int64_t cap = c64 ? 16384 : 8192;
+    d->B_max = n / d->alpha < cap ? n / d->alpha : cap;
+  }
+  if (d->B_max < d->B0) d->B_max = d->B0;
+  d->L_loc = 9;
+  d->L_est = 9;
+  d->T_vote = 5;
+  d->P_max = 12;
+  d->d = 2;
+  d->gamma = 32;
+  d->delta = c64 ? 1e-6 : 1e-8;
+  d->q = 0.1;
+  d->noise_rate = 0.01;
+  d->rho = 1e-6;
+  d->fixed_B = 0;
+  d->fixed_k = 0;
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
+  if (!out) return fail(ATSFFT_EINVAL, "null plan pointer");
+  *out = nullptr;
+  atsfft_status st = validate(d);
+  if (st != ATSFFT_SUCCESS) return st;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(ATSFFT_ENODEVICE, "no HIP device");
+  }
+  atsfft_plan_s *p = new (std::nothrow) atsfft_plan_s();
+  if (!p) return fail(ATSFFT_ENOMEM, "host allocation failed");
+  p->d = *d;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free_plan(p);
+    return fail(ATSFFT_ENODEVICE, "hipGetDevice failed");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+    free_plan(p);
+    return fail(ATSFFT_ENODEVICE, "hipGetDeviceProperties failed");
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    free_plan(p);
+    return fail(ATSFFT_ENODEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  }
+
+  const bool fixed = (d->flags & ATSFFT_FLAG_FIXED_B) != 0;
+  const int64_t n = d->n;
+  p->logn = ilog2_host((uint64_t)n);
+  const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
+  p->Bc_max = (uint32_t)(d->ndim == 1 ? Bbig : Bbig * Bbig);
+  p->bucket_smem = bucket_smem_bytes(d->dtype, p->Bc_max);
+  p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
+  if (p->bucket_smem > prop.sharedMemPerBlock) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "B_max^ndim = %u needs %zu bytes of LDS, device has %zu", p->Bc_max,
+                  p->bucket_smem, (size_t)prop.sharedMemPerBlock);
+    free_plan(p);
+    return fail(ATSFFT_EINVAL, msg);
+  }
+
+  // window tables for every bucket count a loop may use
+  std::vector<double> taps_all, ghat_all;
+  std::vector<int64_t> tab(96, 0);
+  std::vector<double> taps;
+  const int64_t Blo = fixed ? d->fixed_B : d->B0;
+  const int64_t Bhi = fixed ? d->fixed_B : d->B_max;
+  std::vector<int64_t> main_taps_off;
+  double *taps_dev64 = nullptr, *ghat_dev64 = nullptr;
+  for (int64_t B = Blo; B <= Bhi; B *= 2) {
+    const uint32_t lb = ilog2_host((uint64_t)B);
+    if (!fixed) {
+      const int64_t wp = std::min<int64_t>((int64_t)d->alpha_probe * B, n);
+      window_taps(n, B, wp, d->delta, taps);
+      tab[lb] = (int64_t)taps_all.size();
+      taps_all.insert(taps_all.end(), taps.begin(), taps.end());
+    }
+    const int64_t w = std::min<int64_t>((int64_t)d->alpha * B, n);
+    window_taps(n, B, w, d->delta, taps);
+    tab[32 + lb] = (int64_t)taps_all.size();
+    taps_all.insert(taps_all.end(), taps.begin(), taps.end());
+    tab[64 + lb] = (int64_t)ghat_all.size();
+    ghat_all.resize(ghat_all.size() + (size_t)(n / B + 1), 0.0);
+  }
+  // G'(o) from the FP64 taps, on the device
+  if (hipMalloc(&taps_dev64, taps_all.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&ghat_dev64, ghat_all.size() * sizeof(double)) != hipSuccess) {
+    (void)hipFree(taps_dev64);
+    (void)hipFree(ghat_dev64);
+    free_plan(p);
+    return fail(ATSFFT_ENOMEM, "window table allocation failed");
+  }
+  bool ok = hipMemcpy(taps_dev64, taps_all.data(), taps_all.size() * sizeof(double), hipMemcpyHostToDevice) ==
+            hipSuccess;
+  for (int64_t B = Blo; ok && B <= Bhi; B *= 2) {
+    const uint32_t lb = ilog2_host((uint64_t)B);
+    const int64_t w = std::min<int64_t>((int64_t)d->alpha * B, n);
+    ok = launch_window_hat(taps_dev64 + tab[32 + lb], w, n, n / (2 * B), ghat_dev64 + tab[64 + lb], nullptr) ==
+         hipSuccess;
+  }
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  ok = ok && hipMemcpy(ghat_all.data(), ghat_dev64, ghat_all.size() * sizeof(double), hipMemcpyDeviceToHost) ==
+                 hipSuccess;
+  (void)hipFree(taps_dev64);
+  (void)hipFree(ghat_dev64);
+  if (!ok) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return fail(ATSFFT_ELAUNCH, "window table generation failed");
+  }
+  const size_t rs = d->dtype == ATSFFT_C64 ? sizeof(float) : sizeof(double);
+  if (hipMalloc(&p->G_dev, taps_all.size() * rs) != hipSuccess ||
+      hipMalloc(&p->Ghat_dev, ghat_all.size() * rs) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&p->tab_dev), 96 * sizeof(int64_t)) != hipSuccess) {
+    free_plan(p);
+    return fail(ATSFFT_ENOMEM, "window table allocation failed");
+  }
+  if (d->dtype == ATSFFT_C64) {
+    std::vector<float> g = convert<float>(taps_all), gh = convert<float>(ghat_all);
+    ok = hipMemcpy(p->G_dev, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(p->Ghat_dev, gh.data(), gh.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  } else {
+    ok = hipMemcpy(p->G_dev, taps_all.data(), taps_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(p->Ghat_dev, ghat_all.data(), ghat_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  ok = ok && hipMemcpy(p->tab_dev, tab.data(), 96 * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && prepare_kernels(d->dtype, d->ndim, p->bucket_smem, p->est_smem) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return fail(ATSFFT_ELAUNCH, "window table upload or kernel setup failed");
+  }
+  *out = p;
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_workspace_size(atsfft_plan_t plan, int32_t batch, size_t *bytes) {
+  if (!plan || !bytes) return fail(ATSFFT_EINVAL, "null argument");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  *bytes = make_layout(plan, batch).total;
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const void *x_dev, int64_t *locs_dev,
+                                     void *vals_dev, int32_t *count_dev, int32_t *khat_dev,
+                                     uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes,
+                                     hipStream_t stream) {
+  if (!plan) return fail(ATSFFT_EINVAL, "null plan");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  if (!x_dev || !locs_dev || !vals_dev || !count_dev || !khat_dev || !sig_status_dev || !ws_dev)
+    return fail(ATSFFT_EINVAL, "null device pointer");
+  const Layout lay = make_layout(plan, batch);
+  if (ws_bytes < lay.total) return fail(ATSFFT_EINVAL, "workspace too small");
+  const atsfft_desc &d = plan->d;
+  KParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.seed = d.seed;
+  P.n = (uint32_t)d.n;
+  P.logn = plan->logn;
+  P.ndim = (uint32_t)d.ndim;
+  P.Bc_max = plan->Bc_max;
+  P.B0 = (uint32_t)d.B0;
+  P.B_max = (uint32_t)d.B_max;
+  P.alpha_probe = (uint32_t)d.alpha_probe;
+  P.alpha = (uint32_t)d.alpha;
+  P.L_loc = (uint32_t)d.L_loc;
+  P.L_est = (uint32_t)d.L_est;
+  P.T_vote = (uint32_t)d.T_vote;
+  P.P_max = (uint32_t)d.P_max;
+  P.d = (uint32_t)d.d;
+  P.gamma = (uint32_t)d.gamma;
+  P.max_out = (uint32_t)d.max_out;
+  P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
+  P.fixed_B = (uint32_t)d.fixed_B;
+  P.fixed_k = (uint32_t)d.fixed_k;
+  P.q = d.q;
+  P.neg_log1mq = -std::log(1.0 - d.q);
+  P.noise_rate = d.noise_rate;
+  P.rho = d.rho;
+  P.G = plan->G_dev;
+  P.Ghat = plan->Ghat_dev;
+  P.tab = plan->tab_dev;
+  P.ws = static_cast<uint8_t *>(ws_dev);
+  P.lay = lay;
+  P.x = x_dev;
+  P.x_sig = d.ndim == 1 ? d.n : d.n * d.n;
+  P.locs = locs_dev;
+  P.vals = vals_dev;
+  P.count = count_dev;
+  P.khat = khat_dev;
+  P.status = sig_status_dev;
+  if (launch_execute(P, d.dtype, batch, stream) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *locs_dev, void *vals_dev,
+                             int32_t *count_dev, int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev,
+                             size_t ws_bytes, hipStream_t stream) {
+  return atsfft_execute_batched(plan, 1, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev,
+                                ws_dev, ws_bytes, stream);
+}
+
+atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *grad_vals_dev, const void *ws_dev,
+                              void *grad_x_dev, hipStream_t stream) {
+  (void)stream;
+  if (!plan) return fail(ATSFFT_EINVAL, "null plan");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  if (!grad_vals_dev || !ws_dev || !grad_x_dev) return fail(ATSFFT_EINVAL, "null device pointer");
+  return fail(ATSFFT_ENOTSUPPORTED, "the adjoint of value estimation is not provided by this build");
+}
+
+atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t signal, atsfft_trace *out,
+                                hipStream_t stream) {
+  if (!plan || !ws_dev || !out) return fail(ATSFFT_EINVAL, "null argument");
+  if (signal < 0 || signal >= plan->d.max_batch) return fail(ATSFFT_EINVAL, "signal outside [0, max_batch)");
+  const atsfft_desc &d = plan->d;
+  const Layout lay = make_layout(plan, 1);
+  const uint8_t *ws = static_cast<const uint8_t *>(ws_dev) + (size_t)signal * lay.slice;
+  const size_t cs = d.dtype == ATSFFT_C64 ? 8 : 16;
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(ATSFFT_ELAUNCH, "stream synchronisation failed");
+  SigState s;
+  bool ok = hipMemcpy(&s, ws + lay.state, sizeof(s), hipMemcpyDeviceToHost) ==
+            hipSuccess;
+  if (!ok) return fail(ATSFFT_ELAUNCH, "trace copy failed");
+  out->B_star = s.B_star;
+  out->khat = s.khat;
+  out->n_probe = s.n_probe;
+  out->count = (int32_t)s.count;
+  out->status = s.status;
+  if (out->probe_B || out->probe_k || out->probe_dec || out->probe_T) {
+    std::vector<ProbeRec> h((size_t)kMaxProbe);
+    ok = hipMemcpy(h.data(), ws + lay.hist, kMaxProbe * sizeof(ProbeRec),
+                   hipMemcpyDeviceToHost) == hipSuccess;
+    for (int i = 0; ok && i < d.P_max; ++i) {
+      if (out->probe_B) out->probe_B[i] = h[(size_t)i].B;
+      if (out->probe_k) out->probe_k[i] = h[(size_t)i].k;
+      if (out->probe_dec) out->probe_dec[i] = h[(size_t)i].dec;
+      if (out->probe_T) out->probe_T[i] = h[(size_t)i].T;
+    }
+  }
+  if (ok && out->T_loc)
+    ok = hipMemcpy(out->T_loc, ws + lay.tloc, (size_t)d.L_loc * 8,
+                   hipMemcpyDeviceToHost) == hipSuccess;
+  if (ok && out->J_count)
+    ok = hipMemcpy(out->J_count, ws + lay.jcount, (size_t)d.L_loc * 4,
+                   hipMemcpyDeviceToHost) == hipSuccess;
+  if (ok && out->yhat) {
+    const size_t L = (size_t)(d.L_loc + d.L_est);
+    for (size_t l = 0; ok && l < L; ++l)
+      ok = hipMemcpy(static_cast<uint8_t *>(out->yhat) + l * plan->Bc_max * cs,
+                     ws + lay.ymain + l * lay.ymain_loop, plan->Bc_max * cs,
+                     hipMemcpyDeviceToHost) == hipSuccess;
+  }
+  if (ok && out->J_bits) {
+    const size_t words = (plan->Bc_max + 31) / 32;
+    for (int l = 0; ok && l < d.L_loc; ++l)
+      ok = hipMemcpy(out->J_bits + (size_t)l * words, ws + lay.jbits + l * lay.jbits_loop,
+                     words * 4, hipMemcpyDeviceToHost) == hipSuccess;
+  }
+  if (!ok) return fail(ATSFFT_ELAUNCH, "trace copy failed");
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_destroy(atsfft_plan_t plan) {
+  free_plan(plan);
+  return ATSFFT_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal types shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace atsfft {
+
+constexpr int kMaxLoops = 32;        // L_loc, L_est <= 31
+constexpr int kMaxProbe = 32;        // P_max <= 32
+constexpr int kBucketThreads = 1024; // one workgroup per bucket array
+constexpr int kBucketMaxPer = 16;    // bucket values per thread: B^ndim <= 16384
+constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap groups
+constexpr int kHashTile = 64;
+constexpr int kVoteThreads = 256;
+constexpr int kEstThreads = 256;
+constexpr int kMaxOut = 16384;
+
+enum : uint32_t {
+  kSigTruncated = 1,
+  kSigNotConverged = 2,
+  kSigSaturated = 4,
+  kSigEmpty = 8,
+};
+
+enum : int { kPhaseProbe = 0, kPhaseLoc = 1, kPhaseEst = 2 };
+
+// Per-signal control block of the adaptive probe and the vote (device memory).
+struct SigState {
+  int32_t B;        // bucket count (per axis) of the next probe iteration
+  int32_t k_prev;   // previous local-maximum count
+  int32_t done;     // probe finished
+  int32_t B_star;   // bucket count of the location and estimation loops
+  int32_t khat;     // probed sparsity
+  uint32_t status;  // ATSFFT_SIG_* bits
+  uint32_t visited; // bit log2(B) set once B was probed
+  int32_t n_probe;  // probe iterations run
+  uint32_t count;   // |S|, appended by the vote
+  int32_t pad[7];
+};
+static_assert(sizeof(SigState) == 64, "SigState layout");
+
+struct ProbeRec {
+  int32_t B, k, dec, pad;
+  double T;
+  double pad2;
+};
+static_assert(sizeof(ProbeRec) == 32, "ProbeRec layout");
+
+// Workspace layout: one slice of `slice` bytes per signal; the fields are
+// byte offsets inside a slice (and strides between loops).
+struct Layout {
+  size_t slice;
+  size_t state, hist, yprobe, ymain, ymain_loop, tloc, jcount;
+  size_t jbits, jbits_loop, jlist, jlist_loop, S;
+  size_t total;
+};
+
+// Everything a kernel needs, passed by value.
+struct KParams {
+  uint64_t seed;
+  uint32_t n, logn, ndim, Bc_max;
+  uint32_t B0, B_max, alpha_probe, alpha;
+  uint32_t L_loc, L_est, T_vote, P_max, d, gamma, max_out, fixed;
+  uint32_t fixed_B, fixed_k;
+  double q, neg_log1mq, noise_rate, rho;
+  const void *G;       // window taps, plan precision
+  const void *Ghat;    // G'(o) tables, plan precision
+  const int64_t *tab;  // [3][32] element offsets by log2 B: probe taps, main taps, main G'
+  uint8_t *ws;
+  Layout lay;
+  const void *x;
+  int64_t x_sig;       // complex elements per signal
+  int64_t *locs;
+  void *vals;
+  int32_t *count;
+  int32_t *khat;
+  uint32_t *status;
+};
+
+// Host-side launchers (atsfft_kernels.hip).
+hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s);
+hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out,
+                             hipStream_t s);
+hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem);
+size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
+size_t estimate_smem_bytes(uint32_t max_out);
+
+}  // namespace atsfft

@@ -1,0 +1,975 @@
+// gfx950 kernels of ATSFFT (arXiv:1908.02461): the permute/window/fold hash,
+// the LDS-resident bucket DFT with significance threshold, local-maximum count
+// and adaptive-B control, the top-num cutoff, the vote over inverse-permuted
+// buckets, and median value estimation.
+//
+// One batch runs as a fixed sequence of launches on one stream:
+//   k_init                      per-signal control blocks
+//   P_max x { k_hash(probe), k_bucket(probe) }   adaptive probe (Sec. III-A)
+//   k_hash(main)                L_loc + L_est loops at the probed B
+//   k_bucket(main)              bucket DFTs; location loops also select J
+//   k_vote                      located set S (reverse hash, threshold)
+//   k_estimate                  sort S, estimate and take medians
+// Data-dependent sizes (B, |S|) stay on the device: grids are sized for the
+// largest case and workgroups past a signal's actual extent exit at once.
+#include <hip/hip_runtime.h>
+
+#include "atsfft_internal.h"
+
+namespace atsfft {
+
+// ---------------------------------------------------------------- types ----
+
+template <typename R> struct CT;
+template <> struct CT<float> {
+  using C = float2;
+  using K = uint32_t;
+};
+template <> struct CT<double> {
+  using C = double2;
+  using K = unsigned long long;
+};
+
+__device__ __forceinline__ uint32_t key_of(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ unsigned long long key_of(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ float val_of(uint32_t k) { return __uint_as_float(k); }
+__device__ __forceinline__ double val_of(unsigned long long k) { return __longlong_as_double((long long)k); }
+
+__device__ __forceinline__ void sincos_pi(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincos_pi(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// ---------------------------------------------------------------- draws ----
+
+// SplitMix64 (Steele, Lea, Flood 2014): output `index` of the stream seeded
+// with `seed` is the variant-13 finaliser of seed + (index + 1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Draw {
+  uint32_t sigma, tau;
+};
+
+// One loop's permutation (Definition 1) for the key (signal, phase, iteration,
+// axis): sigma odd from the low word, tau from the high word, both mod n.
+__device__ __forceinline__ Draw draw(const KParams &P, uint32_t sig, int phase, int iter, int axis) {
+  const uint64_t index =
+      ((((uint64_t)sig * 4ull + (uint64_t)phase) * 256ull + (uint64_t)iter) * 2ull) + (uint64_t)axis;
+  const uint64_t r = splitmix64_at(P.seed, index);
+  const uint32_t mask = P.n - 1u;
+  Draw d;
+  d.sigma = ((uint32_t)r & mask) | 1u;
+  d.tau = (uint32_t)(r >> 32) & mask;
+  return d;
+}
+
+// Inverse of an odd a modulo 2^32 by Newton's iteration x <- x (2 - a x): the
+// start x = a is right to 3 bits and every step doubles the correct bits.
+__device__ __forceinline__ uint32_t inv_odd(uint32_t a) {
+  uint32_t x = a;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+  return x;
+}
+
+// ------------------------------------------------------------ workspace ----
+
+__device__ __forceinline__ uint8_t *slice_of(const KParams &P, uint32_t sig) {
+  return P.ws + (size_t)sig * P.lay.slice;
+}
+__device__ __forceinline__ SigState *state_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<SigState *>(slice_of(P, sig) + P.lay.state);
+}
+__device__ __forceinline__ ProbeRec *hist_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<ProbeRec *>(slice_of(P, sig) + P.lay.hist);
+}
+template <typename C> __device__ __forceinline__ C *yprobe_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<C *>(slice_of(P, sig) + P.lay.yprobe);
+}
+template <typename C> __device__ __forceinline__ C *ymain_of(const KParams &P, uint32_t sig, uint32_t loop) {
+  return reinterpret_cast<C *>(slice_of(P, sig) + P.lay.ymain + loop * P.lay.ymain_loop);
+}
+__device__ __forceinline__ double *tloc_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<double *>(slice_of(P, sig) + P.lay.tloc);
+}
+__device__ __forceinline__ int32_t *jcount_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<int32_t *>(slice_of(P, sig) + P.lay.jcount);
+}
+__device__ __forceinline__ uint32_t *jbits_of(const KParams &P, uint32_t sig, uint32_t loop) {
+  return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.jbits + loop * P.lay.jbits_loop);
+}
+__device__ __forceinline__ int32_t *jlist_of(const KParams &P, uint32_t sig, uint32_t loop) {
+  return reinterpret_cast<int32_t *>(slice_of(P, sig) + P.lay.jlist + loop * P.lay.jlist_loop);
+}
+__device__ __forceinline__ uint32_t *S_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.S);
+}
+template <typename R>
+__device__ __forceinline__ const R *taps_of(const KParams &P, int which, uint32_t logB) {
+  return reinterpret_cast<const R *>(P.G) + P.tab[which * 32 + logB];
+}
+template <typename R> __device__ __forceinline__ const R *ghat_of(const KParams &P, uint32_t logB) {
+  return reinterpret_cast<const R *>(P.Ghat) + P.tab[64 + logB];
+}
+
+__device__ __forceinline__ uint32_t ilog2(uint32_t v) { return 31u - __clz(v); }
+__device__ __forceinline__ uint32_t bitrev(uint32_t v, uint32_t bits) {
+  return bits ? (__brev(v) >> (32u - bits)) : 0u;
+}
+
+// ------------------------------------------------------- block helpers ----
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Sum over the block; `sh` is one LDS word.  Every thread gets the total.
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
+  if (threadIdx.x == 0) *sh = 0;
+  __syncthreads();
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) atomicAdd(sh, v);
+  __syncthreads();
+  uint32_t r = *sh;
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix sum in thread order; `sh` holds 17 LDS words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) sh[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < nw; ++i) {
+      uint32_t t = sh[i];
+      sh[i] = run;
+      run += t;
+    }
+    sh[16] = run;
+  }
+  __syncthreads();
+  uint32_t r = sh[wv] + incl - v;
+  *total = sh[16];
+  __syncthreads();
+  return r;
+}
+
+// The k-th smallest (0-based) of m[0..cnt) in LDS, by most-significant-digit
+// radix selection on the bit patterns (the values are non-negative, so their
+// patterns order like the values).  `hist` has 256 words, `sh` 2.
+template <typename R>
+__device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
+                                                uint32_t *sh) {
+  using K = typename CT<R>::K;
+  constexpr int NB = sizeof(K) * 8;
+  K prefix = 0, mask = 0;
+  for (int shift = NB - 8; shift >= 0; shift -= 8) {
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
+      const K key = key_of(m[b]);
+      if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const uint32_t l = threadIdx.x;
+      const uint32_t c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+      const uint32_t s = c0 + c1 + c2 + c3;
+      const uint32_t incl = wave_incl_scan(s);
+      const uint32_t excl = incl - s;
+      if (excl <= k && k < incl) {
+        uint32_t digit, run;
+        if (k < excl + c0) {
+          digit = 4 * l;
+          run = excl;
+        } else if (k < excl + c0 + c1) {
+          digit = 4 * l + 1;
+          run = excl + c0;
+        } else if (k < excl + c0 + c1 + c2) {
+          digit = 4 * l + 2;
+          run = excl + c0 + c1;
+        } else {
+          digit = 4 * l + 3;
+          run = excl + c0 + c1 + c2;
+        }
+        sh[0] = digit;
+        sh[1] = k - run;
+      }
+    }
+    __syncthreads();
+    const uint32_t digit = sh[0];
+    k = sh[1];
+    prefix |= (K)digit << shift;
+    mask |= (K)255u << shift;
+    __syncthreads();
+  }
+  return val_of(prefix);
+}
+
+// ------------------------------------------------------------- k_init ----
+
+__global__ void k_init(KParams P, int batch) {
+  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sig >= batch) return;
+  SigState s;
+  s.B = (int32_t)P.B0;
+  s.k_prev = 0;
+  s.done = 0;
+  s.B_star = (int32_t)P.B0;
+  s.khat = 0;
+  s.status = 0;
+  s.visited = 0;
+  s.n_probe = 0;
+  s.count = 0;
+  for (int i = 0; i < 7; ++i) s.pad[i] = 0;
+  if (P.fixed) {
+    s.done = 1;
+    s.B_star = (int32_t)P.fixed_B;
+    s.khat = (int32_t)P.fixed_k;
+    if (s.khat <= 0) s.status |= kSigEmpty;
+  }
+  *state_of(P, sig) = s;
+}
+
+// ------------------------------------------------------------- k_hash ----
+
+// Permute, window and fold one loop (Definition 1, the window paragraph,
+// Lemma 2): y_b = sum over taps t = b mod B, -w/2 <= t < w/2, of
+// x[(sigma t + tau) mod n] G_t.  A workgroup owns 64 buckets; its four
+// 64-lane groups split the w/B wraps of each bucket and a fixed-order LDS
+// sum combines them, so y is written once, with no atomics.  2D: the window
+// is G_{t1} G_{t2} and each axis has its own permutation.
+template <typename R, int NDIM>
+__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter) {
+  using C = typename CT<R>::C;
+  const uint32_t sig = blockIdx.z;
+  const SigState *st = state_of(P, sig);
+  uint32_t B, alpha;
+  int phase, it, which;
+  C *y;
+  if (!main_phase) {
+    if (st->done) return;
+    B = (uint32_t)st->B;
+    alpha = P.alpha_probe;
+    phase = kPhaseProbe;
+    it = iter;
+    which = 0;
+    y = yprobe_of<C>(P, sig);
+  } else {
+    if (st->status & kSigEmpty) return;
+    B = (uint32_t)st->B_star;
+    alpha = P.alpha;
+    which = 1;
+    const uint32_t loop = blockIdx.y;
+    if (loop < P.L_loc) {
+      phase = kPhaseLoc;
+      it = (int)loop;
+    } else {
+      phase = kPhaseEst;
+      it = (int)(loop - P.L_loc);
+    }
+    y = ymain_of<C>(P, sig, blockIdx.y);
+  }
+  const uint32_t logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const uint32_t tile0 = blockIdx.x * kHashTile;
+  if (tile0 >= Bc) return;
+
+  const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t w = min(alpha * B, n);
+  const uint32_t half = w >> 1;
+  const uint32_t wraps = w >> logB;
+  const R *G = taps_of<R>(P, which, logB);
+  const C *x = reinterpret_cast<const C *>(P.x) + (int64_t)sig * P.x_sig;
+  const Draw d0 = draw(P, sig, phase, it, 0);
+  const Draw d1 = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0;
+
+  const uint32_t bi = threadIdx.x & (kHashTile - 1), g = threadIdx.x >> 6;
+  const uint32_t b = tile0 + bi;
+  R ax = 0, ay = 0;
+  if (b < Bc) {
+    if (NDIM == 1) {
+      for (uint32_t r = g; r < wraps; r += 4) {
+        const uint32_t i = b + (r << logB);
+        const uint32_t a = (d0.sigma * (i - half) + d0.tau) & mask;
+        const R gt = G[i];
+        const C xa = x[a];
+        ax += xa.x * gt;
+        ay += xa.y * gt;
+      }
+    } else {
+      const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
+      for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
+        const uint32_t i1 = b1 + (r1 << logB);
+        const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
+        const R g1 = G[i1];
+        const C *row = x + (size_t)a1 * n;
+        for (uint32_t r2 = 0; r2 < wraps; ++r2) {
+          const uint32_t i2 = b2 + (r2 << logB);
+          const uint32_t a2 = (d1.sigma * (i2 - half) + d1.tau) & mask;
+          const R gg = g1 * G[i2];
+          const C xa = row[a2];
+          ax += xa.x * gg;
+          ay += xa.y * gg;
+        }
+      }
+    }
+  }
+  __shared__ R red_x[4][kHashTile], red_y[4][kHashTile];
+  red_x[g][bi] = ax;
+  red_y[g][bi] = ay;
+  __syncthreads();
+  if (g == 0 && b < Bc) {
+    C s;
+    s.x = ((red_x[0][bi] + red_x[1][bi]) + red_x[2][bi]) + red_x[3][bi];
+    s.y = ((red_y[0][bi] + red_y[1][bi]) + red_y[2][bi]) + red_y[3][bi];
+    y[b] = s;
+  }
+}
+
+// --------------------------------------------------------- LDS FFT ----
+
+// Radix-2 decimation-in-time passes along one axis of `count` independent
+// length-2^logB transforms held in LDS in bit-reversed order; element j of
+// transform f sits at buf[f * fstride + j * estride].  Unnormalised, with
+// omega = e^{-2 pi i / B} (the DFT display).
+template <typename R>
+__device__ __forceinline__ void fft_axis(typename CT<R>::C *buf, uint32_t logB, uint32_t count, uint32_t fstride,
+                         uint32_t estride) {
+  using C = typename CT<R>::C;
+  const uint32_t halfB = 1u << (logB - 1);
+  const uint32_t total = count * halfB;
+  for (uint32_t s = 1; s <= logB; ++s) {
+    const uint32_t half = 1u << (s - 1);
+    const R inv_len = (R)1 / (R)(1u << s);
+    for (uint32_t kk = threadIdx.x; kk < total; kk += blockDim.x) {
+      const uint32_t f = kk >> (logB - 1);
+      const uint32_t q = kk & (halfB - 1u);
+      const uint32_t pos = q & (half - 1u);
+      const uint32_t i = ((q >> (s - 1)) << s) + pos;
+      const uint32_t j = i + half;
+      R sn, cs;
+      sincos_pi((R)(-2) * (R)pos * inv_len, &sn, &cs);
+      C *pi = &buf[f * fstride + i * estride];
+      C *pj = &buf[f * fstride + j * estride];
+      const C u = *pi, v = *pj;
+      C vw;
+      vw.x = v.x * cs - v.y * sn;
+      vw.y = v.x * sn + v.y * cs;
+      C o1, o2;
+      o1.x = u.x + vw.x;
+      o1.y = u.y + vw.y;
+      o2.x = u.x - vw.x;
+      o2.y = u.y - vw.y;
+      *pi = o1;
+      *pj = o2;
+    }
+    __syncthreads();
+  }
+}
+
+// key order of the local-maximum and cutoff steps: larger m first, equal m
+// broken by the smaller bucket index
+template <typename R>
+__device__ __forceinline__ bool key_gt(const R *m, uint32_t a, uint32_t b) {
+  const R ma = m[a], mb = m[b];
+  return ma > mb || (ma == mb && a < b);
+}
+
+// B-update rule with the paper's constants (Sec. III-A) in exact integers,
+// D = |k - k_prev|: 100 D < 2 k_prev halves, 100 D < 5 k_prev keeps, else
+// doubles; k_prev = 0 doubles.
+__device__ __forceinline__ int brule(int k_prev, int k) {
+  if (k_prev <= 0) return 1;
+  const long long D = k > k_prev ? k - k_prev : k_prev - k;
+  if (100 * D < 2 * (long long)k_prev) return -1;
+  if (100 * D < 5 * (long long)k_prev) return 0;
+  return 1;
+}
+
+// ------------------------------------------------------------ k_bucket ----
+
+// One workgroup per bucket array: bucket DFT (B or B x B points) in LDS,
+// then for probe and location loops m_b = |y_hat_b|^2, the noise-floor
+// threshold T, and either the local-maximum count with the adaptive-B
+// control (probe) or the top-num cutoff J (location loops).
+template <typename R, int NDIM>
+__global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_phase, int iter) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t sig = blockIdx.y;
+  const uint32_t loop = blockIdx.x;
+  SigState *st = state_of(P, sig);
+  uint32_t B;
+  C *yg;
+  if (!main_phase) {
+    if (st->done) return;
+    B = (uint32_t)st->B;
+    yg = yprobe_of<C>(P, sig);
+  } else {
+    if (st->status & kSigEmpty) return;
+    B = (uint32_t)st->B_star;
+    yg = ymain_of<C>(P, sig, loop);
+  }
+  const uint32_t logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const uint32_t tid = threadIdx.x, T = blockDim.x;
+
+  // bucket DFT
+  C *buf = reinterpret_cast<C *>(smem);
+  for (uint32_t b = tid; b < Bc; b += T) {
+    uint32_t dst;
+    if (NDIM == 1) {
+      dst = bitrev(b, logB);
+    } else {
+      dst = (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
+    }
+    buf[dst] = yg[b];
+  }
+  __syncthreads();
+  if (NDIM == 1) {
+    fft_axis<R>(buf, logB, 1, 0, 1);
+  } else {
+    fft_axis<R>(buf, logB, B, B, 1);
+    fft_axis<R>(buf, logB, B, 1, B);
+  }
+  for (uint32_t b = tid; b < Bc; b += T) yg[b] = buf[b];
+  if (main_phase && loop >= P.L_loc) return;
+
+  // m_b = |y_hat_b|^2 in LDS; it overwrites the front of the DFT buffer, so
+  // every thread reads its values before any is written.
+  const uint32_t per = (Bc + T - 1) / T;
+  R *ms = reinterpret_cast<R *>(smem);
+  {
+    R mv[kBucketMaxPer];
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = tid + (uint32_t)j * T;
+      mv[j] = 0;
+      if ((uint32_t)j < per && b < Bc) {
+        const C v = buf[b];
+        mv[j] = v.x * v.x + v.y * v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = tid + (uint32_t)j * T;
+      if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
+    }
+  }
+  unsigned char *flags = smem + (size_t)Bc * sizeof(R);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + Bc + 15) & ~(size_t)15));
+  uint32_t *sh = hist + 256;  // 32 words of scratch
+  if (tid == 0) {
+    sh[28] = 0;
+    sh[29] = 0;
+  }
+  __syncthreads();
+
+  // threshold: noise floor from the floor(q (Bc-1))-th order statistic,
+  // c_noise = ln(Bc / noise_rate), and the relative floor rho * max m
+  {
+    typename CT<R>::K kmax = 0;
+    for (uint32_t b = tid; b < Bc; b += T) kmax = max(kmax, key_of(ms[b]));
+    for (int o = 32; o > 0; o >>= 1) {
+      typename CT<R>::K other = __shfl_xor(kmax, o);
+      kmax = max(kmax, other);
+    }
+    if ((tid & 63) == 0) {
+      if (sizeof(R) == 4)
+        atomicMax(reinterpret_cast<uint32_t *>(&sh[28]), (uint32_t)kmax);
+      else
+        atomicMax(reinterpret_cast<unsigned long long *>(&sh[28]), (unsigned long long)kmax);
+    }
+  }
+  __syncthreads();
+  R mmax;
+  if (sizeof(R) == 4)
+    mmax = val_of((typename CT<R>::K)sh[28]);
+  else
+    mmax = val_of(*reinterpret_cast<typename CT<R>::K *>(&sh[28]));
+  __syncthreads();
+  const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
+  const R floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh);
+  const double c_noise = log((double)Bc / P.noise_rate);
+  const double t1 = c_noise * ((double)floor_m / P.neg_log1mq);
+  const double t2 = P.rho * (double)mmax;
+  const double Td = t1 > t2 ? t1 : t2;
+  const R Tr = (R)Td;
+
+  if (!main_phase) {
+    // local maxima among significant buckets (1D ring / 2D torus neighbours)
+    uint32_t c = 0;
+    for (uint32_t b = tid; b < Bc; b += T) {
+      if (!(ms[b] > Tr)) continue;
+      bool is_max = true;
+      if (NDIM == 1) {
+        is_max = key_gt(ms, b, (b - 1u) & (B - 1u)) && key_gt(ms, b, (b + 1u) & (B - 1u));
+      } else {
+        const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
+        for (int d1 = -1; d1 <= 1 && is_max; ++d1)
+          for (int d2 = -1; d2 <= 1; ++d2) {
+            if (d1 == 0 && d2 == 0) continue;
+            const uint32_t nb = (((b1 + d1) & (B - 1u)) << logB) | ((b2 + d2) & (B - 1u));
+            if (!key_gt(ms, b, nb)) {
+              is_max = false;
+              break;
+            }
+          }
+      }
+      c += is_max ? 1u : 0u;
+    }
+    const uint32_t k = block_sum(c, &sh[4]);
+    if (tid == 0) {
+      SigState s = *st;
+      ProbeRec *h = hist_of(P, sig) + iter;
+      int dec = iter == 0 ? 1 : brule(s.k_prev, (int)k);
+      // occupancy guard: while fewer than gamma buckets per counted maximum
+      // exist, merges bias the count and the ratio test is not trusted
+      if (P.gamma > 0 && (long long)Bc < (long long)P.gamma * (long long)k) dec = 1;
+      s.visited |= 1u << logB;
+      h->B = (int32_t)B;
+      h->k = (int32_t)k;
+      h->dec = dec;
+      h->T = Td;
+      s.n_probe = iter + 1;
+      bool stop = false;
+      if (dec == 0) {
+        s.B_star = (int32_t)B;
+        s.khat = (int32_t)k;
+        stop = true;
+      } else if (dec < 0) {
+        const uint32_t Bh = B >> 1;
+        const long long Bhc = NDIM == 1 ? (long long)Bh : (long long)Bh * Bh;
+        if (Bh < P.B0 || (P.gamma > 0 && Bhc < (long long)P.gamma * (long long)k)) {
+          s.B_star = (int32_t)B;
+          s.khat = (int32_t)k;
+          stop = true;
+        } else if (s.visited & (1u << (logB - 1))) {
+          s.B_star = (int32_t)Bh;
+          s.khat = (int32_t)k;
+          stop = true;
+        } else {
+          s.B = (int32_t)Bh;
+        }
+      } else {
+        if (2 * B > P.B_max) {
+          s.B_star = (int32_t)B;
+          s.khat = (int32_t)k;
+          s.status |= kSigSaturated;
+          stop = true;
+        } else {
+          s.B = (int32_t)(2 * B);
+        }
+      }
+      if (!stop) {
+        s.k_prev = (int32_t)k;
+        s.B_star = (int32_t)B;
+        s.khat = (int32_t)k;
+        if ((uint32_t)iter + 1 >= P.P_max) {
+          s.status |= kSigNotConverged;
+          stop = true;
+        }
+      }
+      if (stop) {
+        s.done = 1;
+        if (s.khat <= 0) s.status |= kSigEmpty;
+      }
+      *st = s;
+    }
+    return;
+  }
+
+  // location loop: J = the min(num, #{m > T}) largest keys above T
+  uint32_t above = 0;
+  for (uint32_t b = tid; b < Bc; b += T) above += ms[b] > Tr ? 1u : 0u;
+  const uint32_t n_above = block_sum(above, &sh[4]);
+  uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
+  if (num > Bc) num = Bc;
+  // contiguous chunk per thread so that selections come out in index order
+  const uint32_t start = tid * per;
+  const uint32_t cnt = start < Bc ? min(per, Bc - start) : 0u;
+  uint32_t mine = 0;
+  if (n_above <= num) {
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const unsigned char f = ms[start + j] > Tr ? 1 : 0;
+      flags[start + j] = f;
+      mine += f;
+    }
+  } else {
+    const R v = block_kth_smallest<R>(ms, Bc, Bc - num, hist, sh);
+    uint32_t gt = 0, ties = 0;
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const R mj = ms[start + j];
+      gt += mj > v ? 1u : 0u;
+      ties += mj == v ? 1u : 0u;
+    }
+    const uint32_t n_gt = block_sum(gt, &sh[4]);
+    uint32_t tot;
+    uint32_t rank = block_excl_scan(ties, sh + 8, &tot);
+    const uint32_t need = num - n_gt;
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const R mj = ms[start + j];
+      unsigned char f = 0;
+      if (mj > v) {
+        f = 1;
+      } else if (mj == v) {
+        f = rank < need ? 1 : 0;
+        ++rank;
+      }
+      flags[start + j] = f;
+      mine += f;
+    }
+  }
+  uint32_t total;
+  uint32_t pos = block_excl_scan(mine, sh + 8, &total);
+  int32_t *jl = jlist_of(P, sig, loop);
+  for (uint32_t j = 0; j < cnt; ++j)
+    if (flags[start + j]) jl[pos++] = (int32_t)(start + j);
+  __syncthreads();
+  uint32_t *jb = jbits_of(P, sig, loop);
+  const uint32_t words = (Bc + 31) >> 5;
+  for (uint32_t wi = tid; wi < words; wi += T) {
+    uint32_t word = 0;
+    for (uint32_t bb = 0; bb < 32; ++bb) {
+      const uint32_t b = (wi << 5) + bb;
+      if (b < Bc && flags[b]) word |= 1u << bb;
+    }
+    jb[wi] = word;
+  }
+  if (tid == 0) {
+    jcount_of(P, sig)[loop] = (int32_t)total;
+    tloc_of(P, sig)[loop] = Td;
+  }
+}
+
+// -------------------------------------------------------------- k_vote ----
+
+// Reverse hash and vote (Algorithm 1/2): votes(f) = #{l : h_l(f) in J_l},
+// S = {f : votes >= T_vote}.  Any f in S is in J_l for at least one of the
+// first E = L_loc - T_vote + 1 loops, so the candidates are the preimages of
+// those loops' selected buckets; a candidate is emitted only by the first of
+// those loops that holds it, which makes S duplicate-free with no sort and
+// no n-sized histogram.
+template <int NDIM>
+__global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
+  const uint32_t e = blockIdx.y, sig = blockIdx.z;
+  SigState *st = state_of(P, sig);
+  if (st->status & kSigEmpty) return;
+  const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
+  const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
+  const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
+  __shared__ uint32_t s_sig[kMaxLoops][2];
+  if (threadIdx.x < P.L_loc) {
+    s_sig[threadIdx.x][0] = draw(P, sig, kPhaseLoc, threadIdx.x, 0).sigma;
+    s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, threadIdx.x, 1).sigma : 0u;
+  }
+  __syncthreads();
+  const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
+  const int32_t *jl = jlist_of(P, sig, e);
+  const uint32_t inv0 = inv_odd(s_sig[e][0]) & mask;
+  const uint32_t inv1 = NDIM == 2 ? (inv_odd(s_sig[e][1]) & mask) : 0u;
+  const uint32_t *bits0 = jbits_of(P, sig, 0);
+  const uint32_t loop_words = (uint32_t)(P.lay.jbits_loop / 4);
+  const uint32_t L = P.L_loc, Tv = P.T_vote;
+  uint32_t *S = S_of(P, sig);
+
+  auto bucket = [&](uint32_t l, uint32_t f) -> uint32_t {
+    if (NDIM == 1) return ((s_sig[l][0] * f + c) & mask) >> logW;
+    const uint32_t f1 = f >> logn, f2 = f & mask;
+    const uint32_t h1 = ((s_sig[l][0] * f1 + c) & mask) >> logW;
+    const uint32_t h2 = ((s_sig[l][1] * f2 + c) & mask) >> logW;
+    return (h1 << logB) | h2;
+  };
+  auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t {
+    return (bits0[l * loop_words + (h >> 5)] >> (h & 31u)) & 1u;
+  };
+  auto vote_one = [&](uint32_t f) {
+    for (uint32_t e2 = 0; e2 < e; ++e2)
+      if (in_J(e2, bucket(e2, f))) return;
+    uint32_t votes = 0;
+    for (uint32_t l = 0; l < L; ++l) votes += in_J(l, bucket(l, f));
+    if (votes >= Tv) {
+      const uint32_t pos = atomicAdd(&st->count, 1u);
+      if (pos < P.max_out) S[pos] = f;
+    }
+  };
+
+  for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
+    const uint32_t j = (uint32_t)jl[jj];
+    if (NDIM == 1) {
+      const uint32_t p0 = (j << logW) - c;
+      for (uint32_t idx = threadIdx.x; idx < W; idx += blockDim.x) {
+        const uint32_t p = (p0 + idx) & mask;
+        vote_one((inv0 * p) & mask);
+      }
+    } else {
+      const uint32_t j1 = j >> logB, j2 = j & (B - 1u);
+      const uint32_t p01 = (j1 << logW) - c, p02 = (j2 << logW) - c;
+      for (uint32_t idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+        const uint32_t p1 = (p01 + (idx >> logW)) & mask;
+        const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
+        const uint32_t f1 = (inv0 * p1) & mask;
+        const uint32_t f2 = (inv1 * p2) & mask;
+        vote_one((f1 << logn) | f2);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- k_estimate ----
+
+template <typename R, int N> __device__ __forceinline__ void sort_net(R (&a)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const R x = a[i], y = a[l];
+          const R lo = x < y ? x : y, hi = x < y ? y : x;
+          if ((i & k) == 0) {
+            a[i] = lo;
+            a[l] = hi;
+          } else {
+            a[i] = hi;
+            a[l] = lo;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sort S ascending, then for each located f and estimation loop l the
+// estimator display: e_l(f) = y_hat_l[h_l(f)] omega^{tau_l f} / G'(o_l(f)),
+// and the coordinate-wise median over the L_est loops.
+template <typename R, int NDIM, int ML>
+__global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t sig = blockIdx.x;
+  SigState *st = state_of(P, sig);
+  const SigState s = *st;
+  __syncthreads();
+  uint32_t status = s.status;
+  const bool empty = (s.status & kSigEmpty) != 0;
+  const uint32_t count = empty ? 0u : s.count;
+  if (!empty && count > P.max_out) status |= kSigTruncated;
+  if (threadIdx.x == 0) {
+    P.khat[sig] = s.khat;
+    P.count[sig] = (int32_t)count;
+    P.status[sig] = status;
+    st->status = status;
+  }
+  if (empty || count > P.max_out || count == 0) return;
+
+  uint32_t *sS = reinterpret_cast<uint32_t *>(smem);
+  uint32_t P2 = 1;
+  while (P2 < count) P2 <<= 1;
+  const uint32_t *S = S_of(P, sig);
+  for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) sS[i] = i < count ? S[i] : 0xFFFFFFFFu;
+  __syncthreads();
+  for (uint32_t k = 2; k <= P2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const uint32_t a = sS[i], b = sS[l];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            sS[i] = b;
+            sS[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  __shared__ uint32_t es[kMaxLoops][4];
+  if (threadIdx.x < P.L_est) {
+    const Draw d0 = draw(P, sig, kPhaseEst, threadIdx.x, 0);
+    es[threadIdx.x][0] = d0.sigma;
+    es[threadIdx.x][1] = d0.tau;
+    if (NDIM == 2) {
+      const Draw d1 = draw(P, sig, kPhaseEst, threadIdx.x, 1);
+      es[threadIdx.x][2] = d1.sigma;
+      es[threadIdx.x][3] = d1.tau;
+    }
+  }
+  __syncthreads();
+
+  const uint32_t B = (uint32_t)s.B_star, logB = ilog2(B);
+  const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
+  const uint32_t logW = logn - logB, c = (1u << logW) >> 1;
+  const R *gh = ghat_of<R>(P, logB);
+  const R two_over_n = (R)2 / (R)n;
+  int64_t *locs = P.locs + (int64_t)sig * P.max_out;
+  C *vals = reinterpret_cast<C *>(P.vals) + (int64_t)sig * P.max_out;
+  const uint32_t Le = P.L_est;
+
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+    const uint32_t f = sS[i];
+    R re[ML], im[ML];
+#pragma unroll
+    for (int l = 0; l < ML; ++l) {
+      re[l] = (R)INFINITY;
+      im[l] = (R)INFINITY;
+      if ((uint32_t)l < Le) {
+        uint32_t h, phase;
+        R g;
+        if (NDIM == 1) {
+          const uint32_t p = (es[l][0] * f) & mask;
+          h = ((p + c) & mask) >> logW;
+          const uint32_t dd = ((h << logW) - p) & mask;
+          const int o = dd > (n >> 1) ? (int)dd - (int)n : (int)dd;
+          g = gh[o + (int)c];
+          phase = (es[l][1] * f) & mask;
+        } else {
+          const uint32_t f1 = f >> logn, f2 = f & mask;
+          const uint32_t p1 = (es[l][0] * f1) & mask, p2 = (es[l][2] * f2) & mask;
+          const uint32_t h1 = ((p1 + c) & mask) >> logW, h2 = ((p2 + c) & mask) >> logW;
+          const uint32_t dd1 = ((h1 << logW) - p1) & mask, dd2 = ((h2 << logW) - p2) & mask;
+          const int o1 = dd1 > (n >> 1) ? (int)dd1 - (int)n : (int)dd1;
+          const int o2 = dd2 > (n >> 1) ? (int)dd2 - (int)n : (int)dd2;
+          g = gh[o1 + (int)c] * gh[o2 + (int)c];
+          h = (h1 << logB) | h2;
+          phase = ((es[l][1] * f1) + (es[l][3] * f2)) & mask;
+        }
+        const C yv = ymain_of<C>(P, sig, P.L_loc + l)[h];
+        R sn, cs;
+        sincos_pi(-(R)phase * two_over_n, &sn, &cs);
+        const R zr = yv.x * cs - yv.y * sn;
+        const R zi = yv.x * sn + yv.y * cs;
+        re[l] = zr / g;
+        im[l] = zi / g;
+      }
+    }
+    sort_net<R, ML>(re);
+    sort_net<R, ML>(im);
+    locs[i] = (int64_t)f;
+    C v;
+    v.x = re[Le / 2];
+    v.y = im[Le / 2];
+    vals[i] = v;
+  }
+}
+
+// ------------------------------------------------------- window tables ----
+
+// G'(q) = (1/n) sum_t G_t omega^{q t} for the symmetric taps of one window,
+// q in [0, c], written to out[c + q] and out[c - q]; FP64 with the exact
+// integer reduction (q t) mod n before cospi.
+__global__ void k_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > c) return;
+  const int64_t half = w / 2;
+  double acc = taps[half];
+  for (int64_t t = 1; t < half; ++t) {
+    const int64_t m = (q * t) & (n - 1);
+    acc += 2.0 * taps[half + t] * cospi(2.0 * (double)m / (double)n);
+  }
+  const double v = acc / (double)n;
+  out[c + q] = v;
+  out[c - q] = v;
+}
+
+hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out,
+                             hipStream_t s) {
+  const int threads = 256;
+  const int64_t blocks = (c + 1 + threads - 1) / threads;
+  hipLaunchKernelGGL(k_window_hat, dim3((uint32_t)blocks), dim3(threads), 0, s, taps, w, n, c, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ launches ----
+
+size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
+  const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
+  const size_t fft = 2 * rs * Bc_max;
+  const size_t sel = ((rs * Bc_max + Bc_max + 15) & ~(size_t)15) + 4 * (256 + 32);
+  return fft > sel ? fft : sel;
+}
+
+size_t estimate_smem_bytes(uint32_t max_out) {
+  uint32_t p2 = 1;
+  while (p2 < max_out) p2 <<= 1;
+  return 4 * (size_t)p2;
+}
+
+template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t est) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bucket<R, NDIM>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bucket);
+  if (e != hipSuccess) return e;
+  const void *ks[3] = {reinterpret_cast<const void *>(&k_estimate<R, NDIM, 8>),
+                       reinterpret_cast<const void *>(&k_estimate<R, NDIM, 16>),
+                       reinterpret_cast<const void *>(&k_estimate<R, NDIM, 32>)};
+  for (const void *k : ks) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)est);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem) {
+  if (dtype == 0) return ndim == 1 ? set_smem<float, 1>(bucket_smem, est_smem) : set_smem<float, 2>(bucket_smem, est_smem);
+  return ndim == 1 ? set_smem<double, 1>(bucket_smem, est_smem) : set_smem<double, 2>(bucket_smem, est_smem);
+}
+
+template <typename R, int NDIM> static hipError_t run(const KParams &P, int batch, hipStream_t s) {
+  const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
+  const size_t esmem = estimate_smem_bytes(P.max_out);
+  const uint32_t hash_blocks = (P.Bc_max + kHashTile - 1) / kHashTile;
+  hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
+  if (!P.fixed) {
+    for (uint32_t i = 0; i < P.P_max; ++i) {
+      hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, 1, batch), dim3(kHashThreads), 0, s, P, 0,
+                         (int)i);
+      hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(1, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)i);
+    }
+  }
+  const uint32_t loops = P.L_loc + P.L_est;
+  hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, loops, batch), dim3(kHashThreads), 0, s, P, 1, 0);
+  hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
+  const uint32_t E = P.L_loc - P.T_vote + 1;
+  const uint32_t vote_blocks = 64;
+  hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, P);
+  if (P.L_est <= 8)
+    hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, P);
+  else if (P.L_est <= 16)
+    hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(batch), dim3(kEstThreads), esmem, s, P);
+  else
+    hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(batch), dim3(kEstThreads), esmem, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s) {
+  if (dtype == 0) return P.ndim == 1 ? run<float, 1>(P, batch, s) : run<float, 2>(P, batch, s);
+  return P.ndim == 1 ? run<double, 1>(P, batch, s) : run<double, 2>(P, batch, s);
+}
+
+}  // namespace atsfft

@@ -1,0 +1,147 @@
+"""GPU parity: libatsfft.so on an MI355X against the FP64 oracle, same draws.
+
+Each case runs the library through its C ABI and the oracle on identical
+inputs and knobs, then checks every discrete decision (probe bucket counts
+and local-maximum counts, cutoffs, located set, status) for identity and the
+bucket DFTs and values against the tolerance of the precision.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02461_amd import synth
+
+from parity_util import compare, oracle_params, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_02461_amd import atsfft
+
+    atsfft.load()
+    return atsfft
+
+
+def _check_batch(A, plan, xs, label, trace=True):
+    out = run_gpu(plan, np.stack(xs))
+    infos = []
+    for i, x in enumerate(xs):
+        res = plan.results(out, i)
+        tr = plan.trace(out["ws"], i)
+        ref = oracle.atsfft(x, oracle_params(plan, i), trace=True)
+        infos.append(compare(plan, res, tr, ref, f"{label}[{i}]"))
+    print(label, infos, flush=True)
+    return out, infos
+
+
+def test_small_1d_c128_noiseless(A):
+    """n = 2^14, k = 8, |a| = 1, no noise (the small 1D workload)."""
+    n, k = 1 << 14, 8
+    for seed in range(4):
+        plan = A.Plan(1, n, "c128", seed=seed, max_batch=2)
+        xs = [synth.planted_1d(n, k, 100 * seed + i)[0] for i in range(2)]
+        _check_batch(A, plan, xs, f"c1 seed={seed}")
+        out = run_gpu(plan, np.stack(xs))
+        for i in range(2):
+            x, locs, amps = synth.planted_1d(n, k, 100 * seed + i)
+            res = plan.results(out, i)
+            idx = np.searchsorted(res["locs"], locs)
+            assert np.array_equal(res["locs"][idx], locs)
+            assert np.max(np.abs(res["vals"][idx] - amps)) < 1e-9
+
+
+def test_1d_c64_noisy(A):
+    n, k = 1 << 16, 16
+    plan = A.Plan(1, n, "c64", seed=11, max_batch=3)
+    xs = [synth.planted_1d(n, k, s, mag=("uniform", 0.5, 1.0), snr_db=30.0, dtype=np.complex64)[0]
+          for s in range(3)]
+    _check_batch(A, plan, xs, "1d c64 snr30")
+
+
+def test_full_size_1d_c64(A):
+    """n = 2^22, k = 64, |a| in [0.5, 1], SNR 40 dB: the benchmark workload."""
+    n = 1 << 22
+    plan = A.Plan(1, n, "c64", seed=2019, max_batch=2)
+    xs = [synth.make("c2_1d_c64_n4m_k64_snr40", s)[0] for s in (1, 2)]
+    _check_batch(A, plan, xs, "c2 full")
+
+
+def test_small_2d(A):
+    N, k = 256, 4
+    for dt in ("c128", "c64"):
+        plan = A.Plan(2, N, dt, seed=5, max_batch=2, B_max=32)
+        npdt = np.complex128 if dt == "c128" else np.complex64
+        snr = None if dt == "c128" else 40.0
+        mag = None if dt == "c128" else ("uniform", 0.5, 1.0)
+        xs = [synth.planted_2d(N, k, s, mag=mag, snr_db=snr, dtype=npdt)[0] for s in range(2)]
+        _check_batch(A, plan, xs, f"2d {dt}")
+
+
+def test_full_size_2d_c64(A):
+    """4096 x 4096, k = 256, |a| log-uniform in [0.1, 1], SNR 30 dB."""
+    plan = A.Plan(2, 4096, "c64", seed=77, max_batch=1)
+    x = synth.make("c3_2d_c64_n4096_k256_snr30", 3)[0]
+    _check_batch(A, plan, [x], "c3 full")
+
+
+def test_fixed_bucket_count(A):
+    """Algorithm 1 form: the probe is skipped, B and k are given."""
+    n, k = 1 << 14, 8
+    plan = A.Plan(1, n, "c128", seed=3, fixed_B=256, fixed_k=8)
+    x = synth.planted_1d(n, k, 4)[0]
+    _check_batch(A, plan, [x], "fixed B")
+
+
+def test_zero_signal_is_empty(A):
+    n = 1 << 12
+    plan = A.Plan(1, n, "c64", seed=1, max_batch=2, B_max=64)
+    xs = [np.zeros(n, np.complex64), synth.planted_1d(n, 2, 9, dtype=np.complex64)[0]]
+    out, _ = _check_batch(A, plan, xs, "zero + planted")
+    res = plan.results(out, 0)
+    assert res["status"] & A.SIG_EMPTY and res["count"] == 0 and res["khat"] == 0
+
+
+def test_truncated_when_capacity_is_small(A):
+    n, k = 1 << 14, 8
+    plan = A.Plan(1, n, "c128", seed=8, max_out=3)
+    x = synth.planted_1d(n, k, 12)[0]
+    out, _ = _check_batch(A, plan, [x], "truncated")
+    res = plan.results(out, 0)
+    assert res["status"] & A.SIG_TRUNCATED and res["count"] >= k
+
+
+def test_small_bucket_counts_ragged_tiles(A):
+    """B below the 64-bucket hash tile and odd loop counts."""
+    n = 1 << 10
+    plan = A.Plan(1, n, "c128", seed=21, B0=4, B_max=16, alpha=8, alpha_probe=4, gamma=4,
+                  L_loc=5, L_est=3, T_vote=3, max_batch=2)
+    xs = [synth.planted_1d(n, 1, s)[0] for s in range(2)]
+    _check_batch(A, plan, xs, "ragged")
+
+
+@pytest.mark.parametrize("L_est,L_loc,T_vote", [(1, 3, 3), (15, 7, 2), (31, 11, 6)])
+def test_loop_count_variants(A, L_est, L_loc, T_vote):
+    n, k = 1 << 14, 6
+    plan = A.Plan(1, n, "c128", seed=L_est, L_est=L_est, L_loc=L_loc, T_vote=T_vote)
+    x = synth.planted_1d(n, k, 40 + L_est)[0]
+    _check_batch(A, plan, [x], f"loops {L_est}/{L_loc}/{T_vote}")
+
+
+def test_repeat_runs_are_bitwise_identical(A):
+    n = 1 << 16
+    plan = A.Plan(1, n, "c64", seed=99, max_batch=2)
+    xs = np.stack([synth.planted_1d(n, 12, s, mag=("uniform", 0.5, 1.0), snr_db=35.0,
+                                    dtype=np.complex64)[0] for s in range(2)])
+    a = run_gpu(plan, xs)
+    ra = [plan.results(a, i) for i in range(2)]
+    b = run_gpu(plan, xs)
+    rb = [plan.results(b, i) for i in range(2)]
+    for u, v in zip(ra, rb):
+        assert np.array_equal(u["locs"], v["locs"])
+        assert np.array_equal(u["vals"], v["vals"])
