@@ -63,7 +63,18 @@ enum {
 
 /* Descriptor flags. */
 enum {
-  ATSFFT_FLAG_FIXED_B = 1 /* skip the probe: bucket count fixed_B, khat = fixed_k (Algorithm 1) */
+  ATSFFT_FLAG_FIXED_B = 1, /* skip the probe: bucket count fixed_B, khat = fixed_k (Algorithm 1) */
+  ATSFFT_FLAG_PROFILE = 2  /* record stage timing events on every execute (atsfft_profile_read) */
+};
+
+/* Stages timed under ATSFFT_FLAG_PROFILE, in order. */
+enum {
+  ATSFFT_STAGE_PROBE = 0,       /* control init and the adaptive probe iterations */
+  ATSFFT_STAGE_HASH_MAIN = 1,   /* permute/window/fold of the location and estimation loops */
+  ATSFFT_STAGE_BUCKET_MAIN = 2, /* their bucket DFTs and the location-loop cutoffs */
+  ATSFFT_STAGE_VOTE = 3,        /* reverse hash and vote */
+  ATSFFT_STAGE_ESTIMATE = 4,    /* estimation and medians */
+  ATSFFT_NUM_STAGES = 5
 };
 
 /*
@@ -191,6 +202,14 @@ typedef struct atsfft_trace {
 
 atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t signal,
                                 atsfft_trace *out, hipStream_t stream);
+
+/*
+ * Stage durations (milliseconds, HIP events on the execute's stream) summed
+ * over every execute since the previous call, and the number of executes.
+ * Waits for those executes to finish.  stage_ms has ATSFFT_NUM_STAGES
+ * entries.  Without ATSFFT_FLAG_PROFILE it reports zero executes.
+ */
+atsfft_status atsfft_profile_read(atsfft_plan_t plan, double *stage_ms, int32_t *executes);
 
 /* Release the plan's device tables.  Null is accepted. */
 atsfft_status atsfft_destroy(atsfft_plan_t plan);

@@ -20,6 +20,8 @@ SUCCESS, EINVAL, ENODEVICE, ENOMEM, ELAUNCH, ENOTSUPPORTED = range(6)
 C64, C128 = 0, 1
 SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY = 0, 1, 2, 4, 8
 FLAG_FIXED_B = 1
+FLAG_PROFILE = 2
+STAGES = ("probe", "hash_main", "bucket_main", "vote", "estimate")
 
 
 class Desc(C.Structure):
@@ -72,7 +74,7 @@ class Trace(C.Structure):
 EXPORTS = (
     "atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
     "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
-    "atsfft_status_string", "atsfft_version", "atsfft_last_error",
+    "atsfft_status_string", "atsfft_version", "atsfft_last_error", "atsfft_profile_read",
 )
 
 _lib = None
@@ -104,12 +106,14 @@ def load():
     L.atsfft_backward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.atsfft_trace_read.argtypes = [vp, vp, C.c_int32, C.POINTER(Trace), vp]
     L.atsfft_destroy.argtypes = [vp]
+    L.atsfft_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     L.atsfft_status_string.argtypes = [C.c_int]
     L.atsfft_status_string.restype = C.c_char_p
     L.atsfft_version.restype = C.c_char_p
     L.atsfft_last_error.restype = C.c_char_p
     for name in ("atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
-                 "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy"):
+                 "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
+                 "atsfft_profile_read"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -124,12 +128,15 @@ def default_desc(ndim: int, n: int, dtype: str = "c64", **knobs) -> Desc:
     d = Desc()
     _check(load().atsfft_default_desc(C.byref(d), ndim, n, C64 if dtype == "c64" else C128),
            "atsfft_default_desc")
+    profile = bool(knobs.pop("profile", False))
     for k, v in knobs.items():
         if not hasattr(d, k):
             raise TypeError(f"unknown knob {k!r}")
         setattr(d, k, v)
     if knobs.get("fixed_B", 0):
         d.flags |= FLAG_FIXED_B
+    if profile:
+        d.flags |= FLAG_PROFILE
     return d
 
 
@@ -216,8 +223,9 @@ class Plan:
             vals=out["vals"][signal, :kept].cpu().numpy().astype(np.complex128),
         )
 
-    def trace(self, ws, signal: int = 0) -> dict:
-        """atsfft_trace_read: probe history, thresholds, bucket DFTs and cutoffs."""
+    def trace(self, ws, signal: int = 0, full: bool = True) -> dict:
+        """atsfft_trace_read: probe history, thresholds, bucket DFTs and cutoffs
+        (the last two only when ``full``)."""
         import torch
 
         d = self.desc
@@ -240,20 +248,31 @@ class Plan:
         t.probe_T = pT.ctypes.data_as(C.POINTER(C.c_double))
         t.T_loc = tl.ctypes.data_as(C.POINTER(C.c_double))
         t.J_count = jc.ctypes.data_as(C.POINTER(C.c_int32))
-        t.yhat = yh.ctypes.data
-        t.J_bits = jb.ctypes.data_as(C.POINTER(C.c_uint32))
+        if full:
+            t.yhat = yh.ctypes.data
+            t.J_bits = jb.ctypes.data_as(C.POINTER(C.c_uint32))
         s = torch.cuda.current_stream(ws.device).cuda_stream
         _check(load().atsfft_trace_read(self._h, ws.data_ptr(), signal, C.byref(t), s), "atsfft_trace_read")
         npb = int(t.n_probe)
         B = int(t.B_star)
         c = B if self.ndim == 1 else B * B
         bits = np.unpackbits(jb.view(np.uint8), bitorder="little").reshape(d.L_loc, words * 32)
+        if not full:
+            yh, bits = yh[:, :0], bits[:, :0]
+            c = 0
         return dict(
             B_star=B, khat=int(t.khat), n_probe=npb, count=int(t.count), status=int(t.status),
             probe_B=pB[:npb].tolist(), probe_k=pk[:npb].tolist(), probe_decision=pd[:npb].tolist(),
             probe_T=pT[:npb].tolist(), T_loc=tl[: d.L_loc].tolist(), J_count=jc[: d.L_loc].tolist(),
             yhat=yh[:, :c].astype(np.complex128), J=bits[:, :c].astype(bool),
         )
+
+    def profile_read(self) -> dict:
+        """Summed stage times (ms) and execute count since the last read."""
+        ms = (C.c_double * len(STAGES))()
+        cnt = C.c_int32()
+        _check(load().atsfft_profile_read(self._h, ms, C.byref(cnt)), "atsfft_profile_read")
+        return {"executes": int(cnt.value), **{s: float(ms[i]) for i, s in enumerate(STAGES)}}
 
     def backward(self, grad_vals, ws, grad_x, stream=None):
         import torch

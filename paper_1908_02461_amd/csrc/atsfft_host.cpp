@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,8 @@ struct atsfft_plan_s {
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t *tab_dev;  // [96] element offsets by log2 B
   size_t bucket_smem, est_smem;
+  // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
+  std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
 };
 
 namespace {
@@ -154,6 +157,9 @@ template <typename T> std::vector<T> convert(const std::vector<double> &v) {
 
 void free_plan(atsfft_plan_s *p) {
   if (!p) return;
+  for (auto *pool : {&p->prof_used, &p->prof_free})
+    for (auto &rec : *pool)
+      for (hipEvent_t e : rec) (void)hipEventDestroy(e);
   if (p->G_dev) (void)hipFree(p->G_dev);
   if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
   if (p->tab_dev) (void)hipFree(p->tab_dev);
@@ -393,7 +399,29 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
   P.count = count_dev;
   P.khat = khat_dev;
   P.status = sig_status_dev;
-  if (launch_execute(P, d.dtype, batch, stream) != hipSuccess) {
+  std::array<hipEvent_t, 6> *rec = nullptr;
+  if (d.flags & ATSFFT_FLAG_PROFILE) {
+    if (plan->prof_free.empty()) {
+      std::array<hipEvent_t, 6> r;
+      for (auto &e : r)
+        if (hipEventCreate(&e) != hipSuccess) return fail(ATSFFT_ELAUNCH, "hipEventCreate failed");
+      plan->prof_free.push_back(r);
+    }
+    plan->prof_used.push_back(plan->prof_free.back());
+    plan->prof_free.pop_back();
+    rec = &plan->prof_used.back();
+  }
+  struct MarkCtx {
+    std::array<hipEvent_t, 6> *rec;
+    hipStream_t s;
+  } mctx{rec, stream};
+  StageMark mark = nullptr;
+  if (rec)
+    mark = [](void *c, int stage) {
+      MarkCtx *m = static_cast<MarkCtx *>(c);
+      (void)hipEventRecord((*m->rec)[(size_t)stage], m->s);
+    };
+  if (launch_execute(P, d.dtype, batch, stream, mark, &mctx) != hipSuccess) {
     hipError_t e = hipGetLastError();
     return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   }
@@ -465,6 +493,24 @@ atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t 
                      words * 4, hipMemcpyDeviceToHost) == hipSuccess;
   }
   if (!ok) return fail(ATSFFT_ELAUNCH, "trace copy failed");
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_profile_read(atsfft_plan_t plan, double *stage_ms, int32_t *executes) {
+  if (!plan || !stage_ms || !executes) return fail(ATSFFT_EINVAL, "null argument");
+  for (int i = 0; i < ATSFFT_NUM_STAGES; ++i) stage_ms[i] = 0.0;
+  *executes = (int32_t)plan->prof_used.size();
+  for (auto &rec : plan->prof_used) {
+    if (hipEventSynchronize(rec[5]) != hipSuccess) return fail(ATSFFT_ELAUNCH, "hipEventSynchronize failed");
+    for (int i = 0; i < ATSFFT_NUM_STAGES; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, rec[(size_t)i], rec[(size_t)i + 1]) != hipSuccess)
+        return fail(ATSFFT_ELAUNCH, "hipEventElapsedTime failed");
+      stage_ms[i] += (double)ms;
+    }
+  }
+  for (auto &rec : plan->prof_used) plan->prof_free.push_back(rec);
+  plan->prof_used.clear();
   return ATSFFT_SUCCESS;
 }
 

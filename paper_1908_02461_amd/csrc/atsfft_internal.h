@@ -80,7 +80,11 @@ struct KParams {
 };
 
 // Host-side launchers (atsfft_kernels.hip).
-hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s);
+// mark(ctx, i) is called after stage i's launches are enqueued (i = 0 before
+// the first launch; 1 probe, 2 main hash, 3 main bucket DFTs, 4 vote,
+// 5 estimate); it may record an event on the stream.  May be null.
+typedef void (*StageMark)(void *ctx, int stage);
+hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s, StageMark mark, void *ctx);
 hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out,
                              hipStream_t s);
 hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem);

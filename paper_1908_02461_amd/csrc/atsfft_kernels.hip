@@ -940,10 +940,12 @@ hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_s
   return ndim == 1 ? set_smem<double, 1>(bucket_smem, est_smem) : set_smem<double, 2>(bucket_smem, est_smem);
 }
 
-template <typename R, int NDIM> static hipError_t run(const KParams &P, int batch, hipStream_t s) {
+template <typename R, int NDIM>
+static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
   const size_t esmem = estimate_smem_bytes(P.max_out);
   const uint32_t hash_blocks = (P.Bc_max + kHashTile - 1) / kHashTile;
+  if (mark) mark(ctx, 0);
   hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
   if (!P.fixed) {
     for (uint32_t i = 0; i < P.P_max; ++i) {
@@ -952,24 +954,29 @@ template <typename R, int NDIM> static hipError_t run(const KParams &P, int batc
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(1, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)i);
     }
   }
+  if (mark) mark(ctx, 1);
   const uint32_t loops = P.L_loc + P.L_est;
   hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, loops, batch), dim3(kHashThreads), 0, s, P, 1, 0);
+  if (mark) mark(ctx, 2);
   hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
+  if (mark) mark(ctx, 3);
   const uint32_t E = P.L_loc - P.T_vote + 1;
   const uint32_t vote_blocks = 64;
   hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, P);
+  if (mark) mark(ctx, 4);
   if (P.L_est <= 8)
     hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, P);
   else if (P.L_est <= 16)
     hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(batch), dim3(kEstThreads), esmem, s, P);
   else
     hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(batch), dim3(kEstThreads), esmem, s, P);
+  if (mark) mark(ctx, 5);
   return hipGetLastError();
 }
 
-hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s) {
-  if (dtype == 0) return P.ndim == 1 ? run<float, 1>(P, batch, s) : run<float, 2>(P, batch, s);
-  return P.ndim == 1 ? run<double, 1>(P, batch, s) : run<double, 2>(P, batch, s);
+hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s, StageMark mark, void *ctx) {
+  if (dtype == 0) return P.ndim == 1 ? run<float, 1>(P, batch, s, mark, ctx) : run<float, 2>(P, batch, s, mark, ctx);
+  return P.ndim == 1 ? run<double, 1>(P, batch, s, mark, ctx) : run<double, 2>(P, batch, s, mark, ctx);
 }
 
 }  // namespace atsfft
