@@ -4,7 +4,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <array>
 #include <new>
 #include <string>
@@ -24,6 +26,8 @@ struct atsfft_plan_s {
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t *tab_dev;  // [96] element offsets by log2 B
   size_t bucket_smem, est_smem;
+  uint32_t hash_parts;  // persistent hash workgroups per slab
+  uint32_t slab_passes; // main-pass passes per signal
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
 };
@@ -114,6 +118,25 @@ atsfft_status validate(const atsfft_desc *d) {
   return ATSFFT_SUCCESS;
 }
 
+uint32_t probe_levels(const atsfft_plan_s *p) {
+  const atsfft_desc &d = p->d;
+  if (d.flags & ATSFFT_FLAG_FIXED_B) return 0;
+  uint32_t lv = ilog2_host((uint64_t)(d.B_max / d.B0)) + 1;
+  return lv < (uint32_t)d.P_max ? lv : (uint32_t)d.P_max;
+}
+
+// bucket values (per slab) of probe levels below `level`
+uint64_t probe_offset(const atsfft_plan_s *p, uint32_t level) {
+  uint64_t off = 0;
+  for (uint32_t i = 0; i < level; ++i) {
+    const uint64_t B = (uint64_t)p->d.B0 << i;
+    off += p->d.ndim == 1 ? B : B * B;
+  }
+  return off;
+}
+
+uint64_t probe_elems(const atsfft_plan_s *p) { return probe_offset(p, probe_levels(p)); }
+
 Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
   const atsfft_desc &d = p->d;
   const size_t A = 256;
@@ -131,9 +154,11 @@ Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
   off = align_up(off + (size_t)kMaxLoops * 8, A);
   l.jcount = off;
   off = align_up(off + (size_t)kMaxLoops * 4, A);
+  // bucket arrays hold kSlabs partials each (k_hash); the DFT lands in slab 0
+  // probe area: the kSlabs partials of every probe level B0 * 2^i
   l.yprobe = off;
-  off = align_up(off + Bc * cs, A);
-  l.ymain_loop = align_up(Bc * cs, A);
+  off = align_up(off + (size_t)kSlabs * probe_elems(p) * cs, A);
+  l.ymain_loop = align_up((size_t)kSlabs * Bc * cs, A);
   l.ymain = off;
   off = align_up(off + L * l.ymain_loop, A);
   l.jbits_loop = align_up(((Bc + 31) / 32) * 4, 16);
@@ -260,6 +285,24 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
   p->Bc_max = (uint32_t)(d->ndim == 1 ? Bbig : Bbig * Bbig);
   p->bucket_smem = bucket_smem_bytes(d->dtype, p->Bc_max);
+  // persistent main-pass hash grid: kSlabs * hash_parts workgroups, two per
+  // CU, all resident at once so that they walk the batch together
+  p->hash_parts = (uint32_t)std::max(1, prop.multiProcessorCount * 2 / kSlabs);
+  if (const char *env = std::getenv("ATSFFT_HASH_PARTS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 4096) p->hash_parts = (uint32_t)v;
+  }
+  // passes per signal in the main pass: a slab of at most 2 MiB per XCD
+  {
+    const int64_t sig_bytes = (d->ndim == 1 ? n : n * n) * (d->dtype == ATSFFT_C64 ? 8 : 16);
+    uint32_t passes = 1;
+    while (passes < 8 && sig_bytes / (kSlabs * (int64_t)passes) > ((int64_t)2 << 20)) passes *= 2;
+    p->slab_passes = passes;
+  }
+  if (const char *env = std::getenv("ATSFFT_SLAB_PASSES")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v == 1 || v == 2 || v == 4 || v == 8) p->slab_passes = (uint32_t)v;
+  }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
   if (p->bucket_smem > prop.sharedMemPerBlock) {
     char msg[160];
@@ -383,6 +426,11 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
   P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
   P.fixed_B = (uint32_t)d.fixed_B;
   P.fixed_k = (uint32_t)d.fixed_k;
+  P.hash_parts = plan->hash_parts;
+  P.slab_passes = plan->slab_passes;
+  P.probe_levels = probe_levels(plan);
+  for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
+    P.probe_off[i] = i < P.probe_levels ? (uint64_t)kSlabs * probe_offset(plan, i) : 0;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;

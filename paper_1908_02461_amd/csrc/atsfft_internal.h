@@ -12,7 +12,7 @@ constexpr int kMaxProbe = 32;        // P_max <= 32
 constexpr int kBucketThreads = 1024; // one workgroup per bucket array
 constexpr int kBucketMaxPer = 16;    // bucket values per thread: B^ndim <= 16384
 constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap groups
-constexpr int kHashTile = 64;
+constexpr int kSlabs = 8;            // address slabs of a signal, one per XCD
 constexpr int kVoteThreads = 256;
 constexpr int kEstThreads = 256;
 constexpr int kMaxOut = 16384;
@@ -64,6 +64,10 @@ struct KParams {
   uint32_t B0, B_max, alpha_probe, alpha;
   uint32_t L_loc, L_est, T_vote, P_max, d, gamma, max_out, fixed;
   uint32_t fixed_B, fixed_k;
+  uint32_t hash_parts;  // persistent hash grid: kSlabs * hash_parts workgroups
+  uint32_t slab_passes; // main-pass passes per signal (power of two)
+  uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
+  uint64_t probe_off[kMaxProbe];       // complex offset of level i's bucket arrays in the probe area
   double q, neg_log1mq, noise_rate, rho;
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
@@ -90,5 +94,6 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem);
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
 size_t estimate_smem_bytes(uint32_t max_out);
+size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);
 
 }  // namespace atsfft

@@ -5,7 +5,9 @@
 //
 // One batch runs as a fixed sequence of launches on one stream:
 //   k_init                      per-signal control blocks
-//   P_max x { k_hash(probe), k_bucket(probe) }   adaptive probe (Sec. III-A)
+//   rounds of { k_hash(probe), k_bucket(probe), k_probe_control }
+//                               adaptive probe (Sec. III-A), several bucket
+//                               counts per round
 //   k_hash(main)                L_loc + L_est loops at the probed B
 //   k_bucket(main)              bucket DFTs; location loops also select J
 //   k_vote                      located set S (reverse hash, threshold)
@@ -88,8 +90,8 @@ __device__ __forceinline__ SigState *state_of(const KParams &P, uint32_t sig) {
 __device__ __forceinline__ ProbeRec *hist_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<ProbeRec *>(slice_of(P, sig) + P.lay.hist);
 }
-template <typename C> __device__ __forceinline__ C *yprobe_of(const KParams &P, uint32_t sig) {
-  return reinterpret_cast<C *>(slice_of(P, sig) + P.lay.yprobe);
+template <typename C> __device__ __forceinline__ C *yprobe_of(const KParams &P, uint32_t sig, uint32_t level) {
+  return reinterpret_cast<C *>(slice_of(P, sig) + P.lay.yprobe) + P.probe_off[level];
 }
 template <typename C> __device__ __forceinline__ C *ymain_of(const KParams &P, uint32_t sig, uint32_t loop) {
   return reinterpret_cast<C *>(slice_of(P, sig) + P.lay.ymain + loop * P.lay.ymain_loop);
@@ -253,33 +255,54 @@ __global__ void k_init(KParams P, int batch) {
 
 // ------------------------------------------------------------- k_hash ----
 
-// Permute, window and fold one loop (Definition 1, the window paragraph,
-// Lemma 2): y_b = sum over taps t = b mod B, -w/2 <= t < w/2, of
-// x[(sigma t + tau) mod n] G_t.  A workgroup owns 64 buckets; its four
-// 64-lane groups split the w/B wraps of each bucket and a fixed-order LDS
-// sum combines them, so y is written once, with no atomics.  2D: the window
-// is G_{t1} G_{t2} and each axis has its own permutation.
+// Permute, window and fold (Definition 1, the window paragraph, Lemma 2):
+// for every loop, y_b = sum over taps t = b mod B, -w/2 <= t < w/2, of
+// x[(sigma t + tau) mod n] G_t.
+//
+// The gathers are random 8- or 16-byte loads, and what they cost depends on
+// where the line comes from: random loads that hit L2 run about four times
+// faster than loads served by HBM or the Infinity Cache.  A loop touches a
+// random slice of the signal, so most lines are touched by several loops and
+// those touches should hit L2.  The signal is cut into kSlabs address slabs
+// (2D: bands of rows); a workgroup gathers only the samples of one slab, and
+// its slab is its index modulo kSlabs, which under the hardware's round-robin
+// dispatch is its XCD, so each XCD's L2 serves one slab.  The grid is
+// (kSlabs x kTileSlots, loops, signals) and is dispatched signal by signal,
+// so the resident workgroups cover about one signal at a time.
+//
+// A workgroup owns 64-bucket tiles (slot, slot + kTileSlots, ...); its four
+// 64-lane groups split each bucket's w/B wraps and issue their in-slab loads
+// eight wraps at a time; a fixed-order LDS sum combines the groups into the
+// slab's partial y_b.  k_bucket adds the kSlabs partials in slab order.
+constexpr int kTile = 64;        // buckets per tile
+constexpr int kTileSlots = 64;   // tile slots per slab (grid x = kSlabs * kTileSlots)
+constexpr int kHashU = 8;        // wraps whose loads are issued together
+
 template <typename R, int NDIM>
-__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter) {
+__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter, int batch) {
   using C = typename CT<R>::C;
+  (void)batch;
+  const uint32_t slab = blockIdx.x % kSlabs;
+  const uint32_t slot = blockIdx.x / kSlabs;
   const uint32_t sig = blockIdx.z;
   const SigState *st = state_of(P, sig);
   uint32_t B, alpha;
-  int phase, it, which;
+  int phase, it;
   C *y;
+  size_t sstride;
   if (!main_phase) {
-    if (st->done) return;
-    B = (uint32_t)st->B;
+    const uint32_t level = (uint32_t)iter + blockIdx.y;
+    if (st->done || level >= P.probe_levels) return;
+    B = P.B0 << level;
     alpha = P.alpha_probe;
     phase = kPhaseProbe;
-    it = iter;
-    which = 0;
-    y = yprobe_of<C>(P, sig);
+    it = (int)level;
+    y = yprobe_of<C>(P, sig, level);
+    sstride = NDIM == 1 ? B : (size_t)B * B;
   } else {
     if (st->status & kSigEmpty) return;
     B = (uint32_t)st->B_star;
     alpha = P.alpha;
-    which = 1;
     const uint32_t loop = blockIdx.y;
     if (loop < P.L_loc) {
       phase = kPhaseLoc;
@@ -288,62 +311,101 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
       phase = kPhaseEst;
       it = (int)(loop - P.L_loc);
     }
-    y = ymain_of<C>(P, sig, blockIdx.y);
+    y = ymain_of<C>(P, sig, loop);
+    sstride = P.Bc_max;
   }
   const uint32_t logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
-  const uint32_t tile0 = blockIdx.x * kHashTile;
-  if (tile0 >= Bc) return;
-
+  if (slot * kTile >= Bc) return;
   const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t slab_shift = P.logn - 3;  // kSlabs = 8 slabs of n/8 addresses (2D: rows)
   const uint32_t w = min(alpha * B, n);
   const uint32_t half = w >> 1;
   const uint32_t wraps = w >> logB;
-  const R *G = taps_of<R>(P, which, logB);
+  const R *G = taps_of<R>(P, main_phase ? 1 : 0, logB);
   const C *x = reinterpret_cast<const C *>(P.x) + (int64_t)sig * P.x_sig;
   const Draw d0 = draw(P, sig, phase, it, 0);
   const Draw d1 = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0;
+  C *yslab = y + (size_t)slab * sstride;
+  const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
+  const uint32_t step = (d0.sigma << (logB + 2)) & mask;  // address step between a group's wraps
+  __shared__ R red_x[4][kTile], red_y[4][kTile];
 
-  const uint32_t bi = threadIdx.x & (kHashTile - 1), g = threadIdx.x >> 6;
-  const uint32_t b = tile0 + bi;
-  R ax = 0, ay = 0;
-  if (b < Bc) {
-    if (NDIM == 1) {
-      for (uint32_t r = g; r < wraps; r += 4) {
-        const uint32_t i = b + (r << logB);
-        const uint32_t a = (d0.sigma * (i - half) + d0.tau) & mask;
-        const R gt = G[i];
-        const C xa = x[a];
-        ax += xa.x * gt;
-        ay += xa.y * gt;
-      }
-    } else {
-      const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
-      for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
-        const uint32_t i1 = b1 + (r1 << logB);
-        const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
-        const R g1 = G[i1];
-        const C *row = x + (size_t)a1 * n;
-        for (uint32_t r2 = 0; r2 < wraps; ++r2) {
-          const uint32_t i2 = b2 + (r2 << logB);
-          const uint32_t a2 = (d1.sigma * (i2 - half) + d1.tau) & mask;
-          const R gg = g1 * G[i2];
-          const C xa = row[a2];
-          ax += xa.x * gg;
-          ay += xa.y * gg;
+  for (uint32_t tile = slot; tile * kTile < Bc; tile += kTileSlots) {
+    const uint32_t b = tile * kTile + bi;
+    R ax = 0, ay = 0;
+    if (b < Bc) {
+      if (NDIM == 1) {
+        // this group's wraps r = g, g + 4, ...: addresses advance by `step`
+        uint32_t a = (d0.sigma * (b + (g << logB) - half) + d0.tau) & mask;
+        for (uint32_t r0 = g; r0 < wraps; r0 += 4 * kHashU) {
+          uint32_t aa[kHashU];
+          bool pp[kHashU];
+#pragma unroll
+          for (int u = 0; u < kHashU; ++u) {
+            aa[u] = a;
+            pp[u] = r0 + 4u * u < wraps && (a >> slab_shift) == slab;
+            a = (a + step) & mask;
+          }
+          C v[kHashU];
+          R gt[kHashU];
+#pragma unroll
+          for (int u = 0; u < kHashU; ++u) {
+            v[u].x = 0;
+            v[u].y = 0;
+            gt[u] = 0;
+            if (pp[u]) {
+              v[u] = x[aa[u]];
+              gt[u] = G[b + ((r0 + 4u * u) << logB)];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kHashU; ++u) {
+            ax += v[u].x * gt[u];
+            ay += v[u].y * gt[u];
+          }
+        }
+      } else {
+        const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
+        for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
+          const uint32_t i1 = b1 + (r1 << logB);
+          const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
+          if ((a1 >> slab_shift) != slab) continue;
+          const R g1 = G[i1];
+          const C *row = x + (size_t)a1 * n;
+          for (uint32_t r0 = 0; r0 < wraps; r0 += kHashU) {
+            C v[kHashU];
+            R gt[kHashU];
+#pragma unroll
+            for (int u = 0; u < kHashU; ++u) {
+              v[u].x = 0;
+              v[u].y = 0;
+              gt[u] = 0;
+              if (r0 + u < wraps) {
+                const uint32_t i2 = b2 + ((r0 + u) << logB);
+                v[u] = row[(d1.sigma * (i2 - half) + d1.tau) & mask];
+                gt[u] = g1 * G[i2];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < kHashU; ++u) {
+              ax += v[u].x * gt[u];
+              ay += v[u].y * gt[u];
+            }
+          }
         }
       }
     }
-  }
-  __shared__ R red_x[4][kHashTile], red_y[4][kHashTile];
-  red_x[g][bi] = ax;
-  red_y[g][bi] = ay;
-  __syncthreads();
-  if (g == 0 && b < Bc) {
-    C s;
-    s.x = ((red_x[0][bi] + red_x[1][bi]) + red_x[2][bi]) + red_x[3][bi];
-    s.y = ((red_y[0][bi] + red_y[1][bi]) + red_y[2][bi]) + red_y[3][bi];
-    y[b] = s;
+    red_x[g][bi] = ax;
+    red_y[g][bi] = ay;
+    __syncthreads();
+    if (g == 0 && b < Bc) {
+      C s;
+      s.x = ((red_x[0][bi] + red_x[1][bi]) + red_x[2][bi]) + red_x[3][bi];
+      s.y = ((red_y[0][bi] + red_y[1][bi]) + red_y[2][bi]) + red_y[3][bi];
+      yslab[b] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -419,13 +481,14 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t sig = blockIdx.y;
   const uint32_t loop = blockIdx.x;
+  const uint32_t level = (uint32_t)iter + blockIdx.x;
   SigState *st = state_of(P, sig);
   uint32_t B;
   C *yg;
   if (!main_phase) {
-    if (st->done) return;
-    B = (uint32_t)st->B;
-    yg = yprobe_of<C>(P, sig);
+    if (st->done || level >= P.probe_levels) return;
+    B = P.B0 << level;
+    yg = yprobe_of<C>(P, sig, level);
   } else {
     if (st->status & kSigEmpty) return;
     B = (uint32_t)st->B_star;
@@ -433,6 +496,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   }
   const uint32_t logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
   const uint32_t tid = threadIdx.x, T = blockDim.x;
 
   // bucket DFT
@@ -444,7 +508,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     } else {
       dst = (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
     }
-    buf[dst] = yg[b];
+    // the slab partials of k_hash, added in slab order
+    C v = yg[b];
+#pragma unroll
+    for (int sl = 1; sl < kSlabs; ++sl) {
+      const C u = yg[(size_t)sl * sstride + b];
+      v.x += u.x;
+      v.y += u.y;
+    }
+    buf[dst] = v;
   }
   __syncthreads();
   if (NDIM == 1) {
@@ -542,61 +614,11 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     }
     const uint32_t k = block_sum(c, &sh[4]);
     if (tid == 0) {
-      SigState s = *st;
-      ProbeRec *h = hist_of(P, sig) + iter;
-      int dec = iter == 0 ? 1 : brule(s.k_prev, (int)k);
-      // occupancy guard: while fewer than gamma buckets per counted maximum
-      // exist, merges bias the count and the ratio test is not trusted
-      if (P.gamma > 0 && (long long)Bc < (long long)P.gamma * (long long)k) dec = 1;
-      s.visited |= 1u << logB;
+      ProbeRec *h = hist_of(P, sig) + level;
       h->B = (int32_t)B;
       h->k = (int32_t)k;
-      h->dec = dec;
+      h->dec = 0;
       h->T = Td;
-      s.n_probe = iter + 1;
-      bool stop = false;
-      if (dec == 0) {
-        s.B_star = (int32_t)B;
-        s.khat = (int32_t)k;
-        stop = true;
-      } else if (dec < 0) {
-        const uint32_t Bh = B >> 1;
-        const long long Bhc = NDIM == 1 ? (long long)Bh : (long long)Bh * Bh;
-        if (Bh < P.B0 || (P.gamma > 0 && Bhc < (long long)P.gamma * (long long)k)) {
-          s.B_star = (int32_t)B;
-          s.khat = (int32_t)k;
-          stop = true;
-        } else if (s.visited & (1u << (logB - 1))) {
-          s.B_star = (int32_t)Bh;
-          s.khat = (int32_t)k;
-          stop = true;
-        } else {
-          s.B = (int32_t)Bh;
-        }
-      } else {
-        if (2 * B > P.B_max) {
-          s.B_star = (int32_t)B;
-          s.khat = (int32_t)k;
-          s.status |= kSigSaturated;
-          stop = true;
-        } else {
-          s.B = (int32_t)(2 * B);
-        }
-      }
-      if (!stop) {
-        s.k_prev = (int32_t)k;
-        s.B_star = (int32_t)B;
-        s.khat = (int32_t)k;
-        if ((uint32_t)iter + 1 >= P.P_max) {
-          s.status |= kSigNotConverged;
-          stop = true;
-        }
-      }
-      if (stop) {
-        s.done = 1;
-        if (s.khat <= 0) s.status |= kSigEmpty;
-      }
-      *st = s;
     }
     return;
   }
@@ -664,6 +686,78 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   }
 }
 
+// ---------------------------------------------------- k_probe_control ----
+
+// The adaptive-B iteration (Sec. III-A, Algorithm 2) for probe levels
+// [lo, hi), one thread per signal, on the counts k_bucket recorded.  The
+// probe starts at B0 and only doubles until it stops: a halving always lands
+// on a bucket count already probed (or below the occupancy guard, or below
+// B0) and ends the probe there, so iteration i always hashes at B0 * 2^i and
+// the counts of a round can be computed before its decisions are taken.
+// Decisions: the B-update rule in exact integers (D = |k_i - k_{i-1}|: 100 D
+// < 2 k_{i-1} halves, 100 D < 5 k_{i-1} keeps, else doubles; k_{i-1} = 0 and
+// the first iteration double); a count is acted on only once B^ndim >=
+// gamma * k_i; keep stops at B; halve stops at B/2 (k-hat from B); doubling
+// past B_max stops (saturated); P_max iterations stop (not converged).
+template <int NDIM>
+__global__ void k_probe_control(KParams P, int lo, int hi, int batch) {
+  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sig >= batch) return;
+  SigState *st = state_of(P, (uint32_t)sig);
+  SigState s = *st;
+  ProbeRec *hist = hist_of(P, (uint32_t)sig);
+  for (int i = lo; i < hi && !s.done; ++i) {
+    ProbeRec *h = hist + i;
+    const uint32_t B = (uint32_t)s.B;
+    const uint32_t logB = ilog2(B);
+    const long long Bc = NDIM == 1 ? (long long)B : (long long)B * B;
+    const int k = h->k;
+    int dec = i == 0 ? 1 : brule(s.k_prev, k);
+    if (P.gamma > 0 && Bc < (long long)P.gamma * (long long)k) dec = 1;
+    s.visited |= 1u << logB;
+    h->dec = dec;
+    s.n_probe = i + 1;
+    bool stop = false;
+    if (dec == 0) {
+      s.B_star = (int32_t)B;
+      s.khat = k;
+      stop = true;
+    } else if (dec < 0) {
+      const uint32_t Bh = B >> 1;
+      const long long Bhc = NDIM == 1 ? (long long)Bh : (long long)Bh * Bh;
+      s.khat = k;
+      if (Bh < P.B0 || (P.gamma > 0 && Bhc < (long long)P.gamma * (long long)k) || !(s.visited & (1u << (logB - 1))))
+        s.B_star = (int32_t)B;  // the last case cannot occur on the doubling chain
+      else
+        s.B_star = (int32_t)Bh;
+      stop = true;
+    } else {
+      if (2 * B > P.B_max) {
+        s.B_star = (int32_t)B;
+        s.khat = k;
+        s.status |= kSigSaturated;
+        stop = true;
+      } else {
+        s.B = (int32_t)(2 * B);
+      }
+    }
+    if (!stop) {
+      s.k_prev = k;
+      s.B_star = (int32_t)B;
+      s.khat = k;
+      if ((uint32_t)i + 1 >= P.P_max) {
+        s.status |= kSigNotConverged;
+        stop = true;
+      }
+    }
+    if (stop) {
+      s.done = 1;
+      if (s.khat <= 0) s.status |= kSigEmpty;
+    }
+  }
+  *st = s;
+}
+
 // -------------------------------------------------------------- k_vote ----
 
 // Reverse hash and vote (Algorithm 1/2): votes(f) = #{l : h_l(f) in J_l},
@@ -671,28 +765,35 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
 // first E = L_loc - T_vote + 1 loops, so the candidates are the preimages of
 // those loops' selected buckets; a candidate is emitted only by the first of
 // those loops that holds it, which makes S duplicate-free with no sort and
-// no n-sized histogram.
+// no n-sized histogram.  The cutoff bitmaps sit in LDS; a candidate stops
+// being tested once the loops left cannot lift it to T_vote.
 template <int NDIM>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
+  extern __shared__ uint32_t s_bits[];  // [L_loc][words]
   const uint32_t e = blockIdx.y, sig = blockIdx.z;
   SigState *st = state_of(P, sig);
   if (st->status & kSigEmpty) return;
+  const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
+  if (blockIdx.x >= ncand) return;
   const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
   const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
+  const uint32_t L = P.L_loc, Tv = P.T_vote;
+  const uint32_t words = (Bc + 31) >> 5;
   __shared__ uint32_t s_sig[kMaxLoops][2];
-  if (threadIdx.x < P.L_loc) {
+  if (threadIdx.x < L) {
     s_sig[threadIdx.x][0] = draw(P, sig, kPhaseLoc, threadIdx.x, 0).sigma;
     s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, threadIdx.x, 1).sigma : 0u;
   }
+  for (uint32_t i = threadIdx.x; i < L * words; i += blockDim.x) {
+    const uint32_t l = i / words, wi = i - l * words;
+    s_bits[i] = jbits_of(P, sig, l)[wi];
+  }
   __syncthreads();
-  const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
   const int32_t *jl = jlist_of(P, sig, e);
   const uint32_t inv0 = inv_odd(s_sig[e][0]) & mask;
   const uint32_t inv1 = NDIM == 2 ? (inv_odd(s_sig[e][1]) & mask) : 0u;
-  const uint32_t *bits0 = jbits_of(P, sig, 0);
-  const uint32_t loop_words = (uint32_t)(P.lay.jbits_loop / 4);
-  const uint32_t L = P.L_loc, Tv = P.T_vote;
   uint32_t *S = S_of(P, sig);
 
   auto bucket = [&](uint32_t l, uint32_t f) -> uint32_t {
@@ -702,18 +803,22 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
     const uint32_t h2 = ((s_sig[l][1] * f2 + c) & mask) >> logW;
     return (h1 << logB) | h2;
   };
-  auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t {
-    return (bits0[l * loop_words + (h >> 5)] >> (h & 31u)) & 1u;
-  };
+  auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t { return (s_bits[l * words + (h >> 5)] >> (h & 31u)) & 1u; };
   auto vote_one = [&](uint32_t f) {
-    for (uint32_t e2 = 0; e2 < e; ++e2)
-      if (in_J(e2, bucket(e2, f))) return;
-    uint32_t votes = 0;
-    for (uint32_t l = 0; l < L; ++l) votes += in_J(l, bucket(l, f));
-    if (votes >= Tv) {
-      const uint32_t pos = atomicAdd(&st->count, 1u);
-      if (pos < P.max_out) S[pos] = f;
+    // loop e holds f by construction; count the others, stopping once the
+    // remaining loops cannot reach the threshold
+    uint32_t votes = 1, left = L - 1;
+    for (uint32_t l = 0; l < L; ++l) {
+      if (l == e) continue;
+      if (votes + left < Tv) return;
+      votes += in_J(l, bucket(l, f));
+      --left;
     }
+    if (votes < Tv) return;
+    for (uint32_t e2 = 0; e2 < e; ++e2)
+      if (in_J(e2, bucket(e2, f))) return;  // emitted by an earlier loop
+    const uint32_t pos = atomicAdd(&st->count, 1u);
+    if (pos < P.max_out) S[pos] = f;
   };
 
   for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
@@ -915,6 +1020,8 @@ size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   return fft > sel ? fft : sel;
 }
 
+size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max) { return 4 * (size_t)L_loc * ((Bc_max + 31) / 32); }
+
 size_t estimate_smem_bytes(uint32_t max_out) {
   uint32_t p2 = 1;
   while (p2 < max_out) p2 <<= 1;
@@ -924,6 +1031,9 @@ size_t estimate_smem_bytes(uint32_t max_out) {
 template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t est) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bucket<R, NDIM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bucket);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vote<NDIM>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
   if (e != hipSuccess) return e;
   const void *ks[3] = {reinterpret_cast<const void *>(&k_estimate<R, NDIM, 8>),
                        reinterpret_cast<const void *>(&k_estimate<R, NDIM, 16>),
@@ -944,25 +1054,39 @@ template <typename R, int NDIM>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
   const size_t esmem = estimate_smem_bytes(P.max_out);
-  const uint32_t hash_blocks = (P.Bc_max + kHashTile - 1) / kHashTile;
+  const uint32_t hash_blocks = kSlabs * max(1u, min((uint32_t)kTileSlots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
   hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
   if (!P.fixed) {
-    for (uint32_t i = 0; i < P.P_max; ++i) {
-      hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, 1, batch), dim3(kHashThreads), 0, s, P, 0,
-                         (int)i);
-      hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(1, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)i);
+    // rounds of probe levels: every level up to B = 2048 at once, then two
+    // levels per round
+    uint32_t lo = 0;
+    while (lo < P.probe_levels) {
+      uint32_t hi = lo == 0 ? 1 : lo + 2;
+      if (lo == 0)
+        while (hi < P.probe_levels && (P.B0 << hi) <= 2048u) ++hi;
+      hi = min(hi, P.probe_levels);
+      const uint32_t Bt = P.B0 << (hi - 1);
+      const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
+      const uint32_t slots = max(1u, min((uint32_t)kTileSlots, (Bct + kTile - 1) / kTile));
+      hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s, P, 0,
+                         (int)lo, batch);
+      hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
+      hipLaunchKernelGGL((k_probe_control<NDIM>), dim3((batch + 255) / 256), dim3(256), 0, s, P, (int)lo, (int)hi,
+                         batch);
+      lo = hi;
     }
   }
   if (mark) mark(ctx, 1);
   const uint32_t loops = P.L_loc + P.L_est;
-  hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, loops, batch), dim3(kHashThreads), 0, s, P, 1, 0);
+  hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, loops, batch), dim3(kHashThreads), 0, s, P, 1, 0, batch);
   if (mark) mark(ctx, 2);
   hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
   if (mark) mark(ctx, 3);
   const uint32_t E = P.L_loc - P.T_vote + 1;
-  const uint32_t vote_blocks = 64;
-  hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, P);
+  const uint32_t vote_blocks = 16;
+  const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
+  hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, P);
   if (mark) mark(ctx, 4);
   if (P.L_est <= 8)
     hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, P);

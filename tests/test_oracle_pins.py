@@ -392,3 +392,21 @@ def test_parameter_validation(orc):
             setattr(p, k, v)
         with pytest.raises(ValueError):
             orc.atsfft(x if p.n == 1024 else np.zeros(p.n, complex), p)
+
+
+def test_probe_is_a_doubling_chain(orc):
+    """Every probe iteration doubles B until the probe stops (a halving always
+    lands on a bucket count already probed), which lets the library compute
+    several probe levels before taking their decisions."""
+    cases = [(1, 1 << 14, 8, None, None), (1, 1 << 16, 40, ("uniform", 0.5, 1.0), 30.0),
+             (1, 1 << 12, 2, None, 20.0), (2, 256, 6, None, None), (2, 512, 30, ("uniform", 0.5, 1.0), 30.0)]
+    for ndim, n, k, mag, snr in cases:
+        for seed in range(8):
+            gen = synth.planted_1d if ndim == 1 else synth.planted_2d
+            x = gen(n, k, seed, mag=mag, snr_db=snr)[0]
+            kw = dict(alpha=8, alpha_probe=4, B_max=min(n // 8, 128)) if ndim == 2 else {}
+            for gamma in (32, 0):
+                r = orc.atsfft(x, orc.Params.defaults(ndim, n, seed=seed, gamma=gamma, **kw), trace=False)
+                B = r["probe_B"]
+                assert all(B[i + 1] == 2 * B[i] for i in range(len(B) - 1)), (ndim, n, k, seed, gamma, B)
+                assert all(d == 1 for d in r["probe_decision"][:-1])
