@@ -275,7 +275,8 @@ __global__ void k_init(KParams P, int batch) {
 // eight wraps at a time; a fixed-order LDS sum combines the groups into the
 // slab's partial y_b.  k_bucket adds the kSlabs partials in slab order.
 constexpr int kTile = 64;        // buckets per tile
-constexpr int kTileSlots = 64;   // tile slots per slab (grid x = kSlabs * kTileSlots)
+constexpr int kVoteIlp = 4;      // vote candidates tested together
+constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
 template <typename R, int NDIM>
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
   (void)batch;
   const uint32_t slab = blockIdx.x % kSlabs;
   const uint32_t slot = blockIdx.x / kSlabs;
+  const uint32_t nslots = gridDim.x / kSlabs;
   const uint32_t sig = blockIdx.z;
   const SigState *st = state_of(P, sig);
   uint32_t B, alpha;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
   const uint32_t step = (d0.sigma << (logB + 2)) & mask;  // address step between a group's wraps
   __shared__ R red_x[4][kTile], red_y[4][kTile];
 
-  for (uint32_t tile = slot; tile * kTile < Bc; tile += kTileSlots) {
+  for (uint32_t tile = slot; tile * kTile < Bc; tile += nslots) {
     const uint32_t b = tile * kTile + bi;
     R ax = 0, ay = 0;
     if (b < Bc) {
@@ -804,40 +806,70 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
     return (h1 << logB) | h2;
   };
   auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t { return (s_bits[l * words + (h >> 5)] >> (h & 31u)) & 1u; };
-  auto vote_one = [&](uint32_t f) {
-    // loop e holds f by construction; count the others, stopping once the
-    // remaining loops cannot reach the threshold
-    uint32_t votes = 1, left = L - 1;
+  // Candidates are tested kVoteIlp at a time so that their bitmap lookups
+  // overlap.  Loop e holds each candidate by construction; the others are
+  // counted until no candidate of the group can still reach the threshold.
+  constexpr int K = kVoteIlp;
+  auto vote_group = [&](const uint32_t (&f)[K], const bool (&valid)[K]) {
+    uint32_t votes[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) votes[k] = valid[k] ? 1u : 0u;
+    uint32_t left = L - 1;
     for (uint32_t l = 0; l < L; ++l) {
       if (l == e) continue;
-      if (votes + left < Tv) return;
-      votes += in_J(l, bucket(l, f));
+      bool live = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) live |= valid[k] && votes[k] + left >= Tv;
+      if (!live) return;
+      uint32_t h[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) h[k] = bucket(l, f[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) votes[k] += in_J(l, h[k]);
       --left;
     }
-    if (votes < Tv) return;
-    for (uint32_t e2 = 0; e2 < e; ++e2)
-      if (in_J(e2, bucket(e2, f))) return;  // emitted by an earlier loop
-    const uint32_t pos = atomicAdd(&st->count, 1u);
-    if (pos < P.max_out) S[pos] = f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!valid[k] || votes[k] < Tv) continue;
+      bool earlier = false;
+      for (uint32_t e2 = 0; e2 < e && !earlier; ++e2) earlier = in_J(e2, bucket(e2, f[k])) != 0u;
+      if (earlier) continue;  // emitted by an earlier loop
+      const uint32_t pos = atomicAdd(&st->count, 1u);
+      if (pos < P.max_out) S[pos] = f[k];
+    }
   };
 
+  const uint32_t T = blockDim.x;
   for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
     const uint32_t j = (uint32_t)jl[jj];
     if (NDIM == 1) {
       const uint32_t p0 = (j << logW) - c;
-      for (uint32_t idx = threadIdx.x; idx < W; idx += blockDim.x) {
-        const uint32_t p = (p0 + idx) & mask;
-        vote_one((inv0 * p) & mask);
+      for (uint32_t i0 = threadIdx.x; i0 < W; i0 += K * T) {
+        uint32_t f[K];
+        bool valid[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t idx = i0 + (uint32_t)k * T;
+          valid[k] = idx < W;
+          f[k] = (inv0 * ((p0 + idx) & mask)) & mask;
+        }
+        vote_group(f, valid);
       }
     } else {
       const uint32_t j1 = j >> logB, j2 = j & (B - 1u);
       const uint32_t p01 = (j1 << logW) - c, p02 = (j2 << logW) - c;
-      for (uint32_t idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        const uint32_t p1 = (p01 + (idx >> logW)) & mask;
-        const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
-        const uint32_t f1 = (inv0 * p1) & mask;
-        const uint32_t f2 = (inv1 * p2) & mask;
-        vote_one((f1 << logn) | f2);
+      for (uint32_t i0 = threadIdx.x; i0 < W * W; i0 += K * T) {
+        uint32_t f[K];
+        bool valid[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t idx = i0 + (uint32_t)k * T;
+          valid[k] = idx < W * W;
+          const uint32_t p1 = (p01 + (idx >> logW)) & mask;
+          const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
+          f[k] = (((inv0 * p1) & mask) << logn) | ((inv1 * p2) & mask);
+        }
+        vote_group(f, valid);
       }
     }
   }
@@ -1054,7 +1086,7 @@ template <typename R, int NDIM>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
   const size_t esmem = estimate_smem_bytes(P.max_out);
-  const uint32_t hash_blocks = kSlabs * max(1u, min((uint32_t)kTileSlots, (P.Bc_max + kTile - 1) / kTile));
+  const uint32_t hash_blocks = kSlabs * max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
   hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
   if (!P.fixed) {
@@ -1068,7 +1100,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hi = min(hi, P.probe_levels);
       const uint32_t Bt = P.B0 << (hi - 1);
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
-      const uint32_t slots = max(1u, min((uint32_t)kTileSlots, (Bct + kTile - 1) / kTile));
+      const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
       hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s, P, 0,
                          (int)lo, batch);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
@@ -1084,7 +1116,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
   if (mark) mark(ctx, 3);
   const uint32_t E = P.L_loc - P.T_vote + 1;
-  const uint32_t vote_blocks = 16;
+  const uint32_t vote_blocks = 32;
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, P);
   if (mark) mark(ctx, 4);
