@@ -61,6 +61,37 @@ def oracle_params(desc, signal):
         seed=desc.seed, signal=signal, max_out=desc.max_out)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hash_main_c2_n4m_k64_b32_hbm_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1908_02461_amd", "csrc", "atsfft_kernels.hip")
+
+
+def hash_kernel_sha256():
+    """SHA-256 of the k_hash section of the kernel source."""
+    import hashlib
+
+    src = open(KERNEL_SRC).read()
+    a = src.index("// " + "-" * 61 + " k_hash ----")
+    b = src.index("// " + "-" * 57 + " LDS FFT ----")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(batch):
+    """HBM bytes per main-hash launch from the committed counter summary, if
+    it was taken on the current k_hash source and batch; otherwise None."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("k_hash_source_sha256") != hash_kernel_sha256() or int(kv.get("batch", -1)) != batch:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(desc, xs, budget_s):
     """The FP64 oracle, single-threaded, on the first signals of the batch."""
     import oracle
@@ -86,6 +117,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--error-signals", type=int, default=4)
+    ap.add_argument("--no-per-signal", action="store_true", help="skip the plain per-signal form")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the transform of one signal does not span GPUs "
@@ -165,9 +199,11 @@ def main():
         for xi in xs1:
             plan1.execute_batched(xi, out=out1, ws=ws1)
 
-    per_signal()
-    log("per-signal form")
-    ms_single = timed(per_signal, max(1, args.steps // 5), stream) / batch
+    ms_single = None
+    if not args.no_per_signal:
+        per_signal()
+        log("per-signal form")
+        ms_single = timed(per_signal, max(1, args.steps // 5), stream) / batch
 
     # same-GPU dense FFT (rocFFT through torch.fft) on the same batch
     y = torch.empty_like(x)
@@ -197,6 +233,13 @@ def main():
         errs_truth.append(e / k)
         recovered.append(float(np.mean(hit)))
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -218,7 +261,7 @@ def main():
         "config": {"workload": WORKLOAD, "n": n, "k": k, "snr_db": 40.0, "batch": batch,
                    "magnitudes": "uniform[0.5,1]", "input": "c64", "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(batch),
                      "kernel": "k_hash (main loops)", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": stage_ms["hash_main"]},
         "cpu_baseline": cpu,
@@ -226,6 +269,7 @@ def main():
         "atsfft_ms_per_transform": ms_step / batch,
         "speedup_vs_dense_fft": ms_dense / ms_step,
         "per_signal_ms_per_transform": ms_single,
+        "k_hash_source_sha256": hash_kernel_sha256(),
         "stage_ms_per_step": stage_ms,
         "profiled_ms_per_step": ms_prof,
         "l1_error": float(np.mean(errs)) if errs else None,

@@ -29,6 +29,7 @@ struct atsfft_plan_s {
   uint32_t hash_parts;  // persistent hash workgroups per slab
   uint32_t slab_passes; // main-pass passes per signal
   uint32_t tile_slots;  // hash workgroups per slab and loop
+  uint32_t hash_loops;  // main-pass loops per hash workgroup
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
 };
@@ -300,6 +301,11 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     while (passes < 8 && sig_bytes / (kSlabs * (int64_t)passes) > ((int64_t)2 << 20)) passes *= 2;
     p->slab_passes = passes;
   }
+  p->hash_loops = 1;
+  if (const char *env = std::getenv("ATSFFT_HASH_LOOPS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 3) p->hash_loops = (uint32_t)v;
+  }
   p->tile_slots = 32;
   if (const char *env = std::getenv("ATSFFT_TILE_SLOTS")) {
     const long v = std::strtol(env, nullptr, 10);
@@ -435,6 +441,7 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
   P.hash_parts = plan->hash_parts;
   P.slab_passes = plan->slab_passes;
   P.tile_slots = plan->tile_slots;
+  P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
   for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
     P.probe_off[i] = i < P.probe_levels ? (uint64_t)kSlabs * probe_offset(plan, i) : 0;

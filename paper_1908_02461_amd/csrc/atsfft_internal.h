@@ -67,6 +67,7 @@ struct KParams {
   uint32_t hash_parts;  // persistent hash grid: kSlabs * hash_parts workgroups
   uint32_t slab_passes; // main-pass passes per signal (power of two)
   uint32_t tile_slots;  // hash tile slots per slab
+  uint32_t hash_loops;  // main-pass loops per hash workgroup (1D: 1..3)
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
   uint64_t probe_off[kMaxProbe];       // complex offset of level i's bucket arrays in the probe area
   double q, neg_log1mq, noise_rate, rho;

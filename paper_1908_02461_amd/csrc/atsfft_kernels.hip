@@ -279,41 +279,45 @@ constexpr int kVoteIlp = 4;      // vote candidates tested together
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
-template <typename R, int NDIM>
+template <typename R, int NDIM, int LG>
 __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter, int batch) {
   using C = typename CT<R>::C;
   (void)batch;
+  static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
   const uint32_t slab = blockIdx.x % kSlabs;
   const uint32_t slot = blockIdx.x / kSlabs;
   const uint32_t nslots = gridDim.x / kSlabs;
   const uint32_t sig = blockIdx.z;
   const SigState *st = state_of(P, sig);
-  uint32_t B, alpha;
-  int phase, it;
-  C *y;
+  uint32_t B, alpha, nl = 1;
+  Draw d0[LG], d1[LG];
+  C *y[LG];
   size_t sstride;
   if (!main_phase) {
     const uint32_t level = (uint32_t)iter + blockIdx.y;
     if (st->done || level >= P.probe_levels) return;
     B = P.B0 << level;
     alpha = P.alpha_probe;
-    phase = kPhaseProbe;
-    it = (int)level;
-    y = yprobe_of<C>(P, sig, level);
+    d0[0] = draw(P, sig, kPhaseProbe, (int)level, 0);
+    d1[0] = NDIM == 2 ? draw(P, sig, kPhaseProbe, (int)level, 1) : d0[0];
+    y[0] = yprobe_of<C>(P, sig, level);
     sstride = NDIM == 1 ? B : (size_t)B * B;
   } else {
     if (st->status & kSigEmpty) return;
     B = (uint32_t)st->B_star;
     alpha = P.alpha;
-    const uint32_t loop = blockIdx.y;
-    if (loop < P.L_loc) {
-      phase = kPhaseLoc;
-      it = (int)loop;
-    } else {
-      phase = kPhaseEst;
-      it = (int)(loop - P.L_loc);
+    const uint32_t loops = P.L_loc + P.L_est;
+    const uint32_t l0 = blockIdx.y * LG;
+    nl = min((uint32_t)LG, loops - l0);
+#pragma unroll
+    for (int q = 0; q < LG; ++q) {
+      const uint32_t loop = min(l0 + q, loops - 1);
+      const int phase = loop < P.L_loc ? kPhaseLoc : kPhaseEst;
+      const int it = loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc);
+      d0[q] = draw(P, sig, phase, it, 0);
+      d1[q] = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0[q];
+      y[q] = ymain_of<C>(P, sig, loop);
     }
-    y = ymain_of<C>(P, sig, loop);
     sstride = P.Bc_max;
   }
   const uint32_t logB = ilog2(B);
@@ -326,52 +330,57 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
   const uint32_t wraps = w >> logB;
   const R *G = taps_of<R>(P, main_phase ? 1 : 0, logB);
   const C *x = reinterpret_cast<const C *>(P.x) + (int64_t)sig * P.x_sig;
-  const Draw d0 = draw(P, sig, phase, it, 0);
-  const Draw d1 = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0;
-  C *yslab = y + (size_t)slab * sstride;
   const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
-  const uint32_t step = (d0.sigma << (logB + 2)) & mask;  // address step between a group's wraps
-  __shared__ R red_x[4][kTile], red_y[4][kTile];
+  __shared__ R red_x[LG][4][kTile], red_y[LG][4][kTile];
 
   for (uint32_t tile = slot; tile * kTile < Bc; tile += nslots) {
     const uint32_t b = tile * kTile + bi;
-    R ax = 0, ay = 0;
+    R ax[LG], ay[LG];
+#pragma unroll
+    for (int q = 0; q < LG; ++q) ax[q] = ay[q] = 0;
     if (b < Bc) {
       if (NDIM == 1) {
-        // this group's wraps r = g, g + 4, ...: addresses advance by `step`
-        uint32_t a = (d0.sigma * (b + (g << logB) - half) + d0.tau) & mask;
+        // the group's wraps r = g, g + 4, ...: addresses advance by sigma * 4B;
+        // the in-slab loads of all the workgroup's loops go out together
+        uint32_t a[LG], step[LG];
+#pragma unroll
+        for (int q = 0; q < LG; ++q) {
+          a[q] = (d0[q].sigma * (b + (g << logB) - half) + d0[q].tau) & mask;
+          step[q] = (d0[q].sigma << (logB + 2)) & mask;
+        }
         for (uint32_t r0 = g; r0 < wraps; r0 += 4 * kHashU) {
-          uint32_t aa[kHashU];
-          bool pp[kHashU];
+          C v[LG][kHashU];
+          R gt[LG][kHashU];
 #pragma unroll
-          for (int u = 0; u < kHashU; ++u) {
-            aa[u] = a;
-            pp[u] = r0 + 4u * u < wraps && (a >> slab_shift) == slab;
-            a = (a + step) & mask;
-          }
-          C v[kHashU];
-          R gt[kHashU];
+          for (int q = 0; q < LG; ++q) {
 #pragma unroll
-          for (int u = 0; u < kHashU; ++u) {
-            v[u].x = 0;
-            v[u].y = 0;
-            gt[u] = 0;
-            if (pp[u]) {
-              v[u] = x[aa[u]];
-              gt[u] = G[b + ((r0 + 4u * u) << logB)];
+            for (int u = 0; u < kHashU; ++u) {
+              const uint32_t aq = a[q];
+              const bool pp = (uint32_t)q < nl && r0 + 4u * u < wraps && (aq >> slab_shift) == slab;
+              a[q] = (aq + step[q]) & mask;
+              v[q][u].x = 0;
+              v[q][u].y = 0;
+              gt[q][u] = 0;
+              if (pp) {
+                v[q][u] = x[aq];
+                gt[q][u] = G[b + ((r0 + 4u * u) << logB)];
+              }
             }
           }
 #pragma unroll
-          for (int u = 0; u < kHashU; ++u) {
-            ax += v[u].x * gt[u];
-            ay += v[u].y * gt[u];
+          for (int q = 0; q < LG; ++q) {
+#pragma unroll
+            for (int u = 0; u < kHashU; ++u) {
+              ax[q] += v[q][u].x * gt[q][u];
+              ay[q] += v[q][u].y * gt[q][u];
+            }
           }
         }
       } else {
         const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
         for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
           const uint32_t i1 = b1 + (r1 << logB);
-          const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
+          const uint32_t a1 = (d0[0].sigma * (i1 - half) + d0[0].tau) & mask;
           if ((a1 >> slab_shift) != slab) continue;
           const R g1 = G[i1];
           const C *row = x + (size_t)a1 * n;
@@ -385,27 +394,35 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
               gt[u] = 0;
               if (r0 + u < wraps) {
                 const uint32_t i2 = b2 + ((r0 + u) << logB);
-                v[u] = row[(d1.sigma * (i2 - half) + d1.tau) & mask];
+                v[u] = row[(d1[0].sigma * (i2 - half) + d1[0].tau) & mask];
                 gt[u] = g1 * G[i2];
               }
             }
 #pragma unroll
             for (int u = 0; u < kHashU; ++u) {
-              ax += v[u].x * gt[u];
-              ay += v[u].y * gt[u];
+              ax[0] += v[u].x * gt[u];
+              ay[0] += v[u].y * gt[u];
             }
           }
         }
       }
     }
-    red_x[g][bi] = ax;
-    red_y[g][bi] = ay;
+#pragma unroll
+    for (int q = 0; q < LG; ++q) {
+      red_x[q][g][bi] = ax[q];
+      red_y[q][g][bi] = ay[q];
+    }
     __syncthreads();
     if (g == 0 && b < Bc) {
-      C s;
-      s.x = ((red_x[0][bi] + red_x[1][bi]) + red_x[2][bi]) + red_x[3][bi];
-      s.y = ((red_y[0][bi] + red_y[1][bi]) + red_y[2][bi]) + red_y[3][bi];
-      yslab[b] = s;
+#pragma unroll
+      for (int q = 0; q < LG; ++q) {
+        if ((uint32_t)q < nl) {
+          C s;
+          s.x = ((red_x[q][0][bi] + red_x[q][1][bi]) + red_x[q][2][bi]) + red_x[q][3][bi];
+          s.y = ((red_y[q][0][bi] + red_y[q][1][bi]) + red_y[q][2][bi]) + red_y[q][3][bi];
+          y[q][(size_t)slab * sstride + b] = s;
+        }
+      }
     }
     __syncthreads();
   }
@@ -1019,16 +1036,27 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
 // ------------------------------------------------------- window tables ----
 
 // G'(q) = (1/n) sum_t G_t omega^{q t} for the symmetric taps of one window,
-// q in [0, c], written to out[c + q] and out[c - q]; FP64 with the exact
-// integer reduction (q t) mod n before cospi.
+// q in [0, c], written to out[c + q] and out[c - q]; FP64.  cos(2 pi q t / n)
+// is evaluated exactly (integer reduction of q t mod n, then cospi) at every
+// 32nd tap and advanced by a rotation through the angle 2 pi q / n in
+// between, which keeps the error of each term within a few 1e-16.
 __global__ void k_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q > c) return;
   const int64_t half = w / 2;
+  double rs, rc;
+  sincospi(2.0 * (double)q / (double)n, &rs, &rc);
   double acc = taps[half];
-  for (int64_t t = 1; t < half; ++t) {
-    const int64_t m = (q * t) & (n - 1);
-    acc += 2.0 * taps[half + t] * cospi(2.0 * (double)m / (double)n);
+  for (int64_t t0 = 1; t0 < half; t0 += 32) {
+    double sn, cs;
+    sincospi(2.0 * (double)((q * t0) & (n - 1)) / (double)n, &sn, &cs);
+    const int64_t t1 = t0 + 32 < half ? t0 + 32 : half;
+    for (int64_t t = t0; t < t1; ++t) {
+      acc += 2.0 * taps[half + t] * cs;
+      const double c2 = cs * rc - sn * rs;
+      sn = sn * rc + cs * rs;
+      cs = c2;
+    }
   }
   const double v = acc / (double)n;
   out[c + q] = v;
@@ -1101,8 +1129,8 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       const uint32_t Bt = P.B0 << (hi - 1);
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
       const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
-      hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s, P, 0,
-                         (int)lo, batch);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s, P,
+                         0, (int)lo, batch);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       hipLaunchKernelGGL((k_probe_control<NDIM>), dim3((batch + 255) / 256), dim3(256), 0, s, P, (int)lo, (int)hi,
                          batch);
@@ -1111,7 +1139,14 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   }
   if (mark) mark(ctx, 1);
   const uint32_t loops = P.L_loc + P.L_est;
-  hipLaunchKernelGGL((k_hash<R, NDIM>), dim3(hash_blocks, loops, batch), dim3(kHashThreads), 0, s, P, 1, 0, batch);
+  const uint32_t LG = NDIM == 1 ? P.hash_loops : 1u;
+  const dim3 hgrid(hash_blocks, (loops + LG - 1) / LG, batch);
+  if (NDIM == 2 || LG == 1)
+    hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
+  else if (LG == 2)
+    hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
+  else
+    hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
   if (mark) mark(ctx, 2);
   hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
   if (mark) mark(ctx, 3);
