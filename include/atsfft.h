@@ -173,9 +173,20 @@ atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *loc
                              hipStream_t stream);
 
 /*
- * Gradient of a real loss through the value estimates at fixed located
- * frequencies and median choices.  Not provided by this build: returns
- * ATSFFT_ENOTSUPPORTED after validating its arguments.
+ * Gradient of a real loss L through the values of the last execute that used
+ * ws_dev, at its located frequencies and median choices held fixed (the
+ * located set and the medians are piecewise constant in x; on each piece the
+ * values are real-linear in x).  Each value is the coordinate-wise median of
+ * the estimator display (Sec. II-B): its real part comes from one estimation
+ * loop and its imaginary part from one (recorded by the execute).  Inputs:
+ *   grad_vals_dev  complex [batch][max_out]: dL/dRe v + i dL/dIm v for each
+ *                  value (entries at or past a signal's count are ignored);
+ *   ws_dev         the execute's workspace, unchanged since.
+ * Output grad_x_dev, complex, the layout of x: dL/dRe x + i dL/dIm x, written
+ * in full (zero where no estimation loop samples).  Signals that were EMPTY
+ * or TRUNCATED get a zero gradient.  Contributions of different loops to one
+ * address are added with atomics, so the last bits may vary between calls.
+ * Errors: ATSFFT_EINVAL, ATSFFT_ELAUNCH.
  */
 atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *grad_vals_dev,
                               const void *ws_dev, void *grad_x_dev, hipStream_t stream);

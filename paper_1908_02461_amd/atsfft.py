@@ -182,8 +182,8 @@ class Plan:
         import torch
 
         return dict(
-            locs=torch.empty((batch, self.max_out), dtype=torch.int64, device=device),
-            vals=torch.empty((batch, self.max_out), dtype=self.torch_dtype, device=device),
+            locs=torch.zeros((batch, self.max_out), dtype=torch.int64, device=device),
+            vals=torch.zeros((batch, self.max_out), dtype=self.torch_dtype, device=device),
             count=torch.empty(batch, dtype=torch.int32, device=device),
             khat=torch.empty(batch, dtype=torch.int32, device=device),
             status=torch.empty(batch, dtype=torch.int32, device=device),
@@ -275,8 +275,13 @@ class Plan:
         return {"executes": int(cnt.value), **{s: float(ms[i]) for i, s in enumerate(STAGES)}}
 
     def backward(self, grad_vals, ws, grad_x, stream=None):
+        """atsfft_backward: grad_x (written in full) from grad_vals [batch, max_out]."""
         import torch
 
+        if grad_vals.dtype != self.torch_dtype or grad_x.dtype != self.torch_dtype:
+            raise ValueError("grad_vals and grad_x must have the plan's complex dtype")
+        if not (grad_vals.is_contiguous() and grad_x.is_contiguous()):
+            raise ValueError("grad_vals and grad_x must be contiguous")
         s = stream if stream is not None else torch.cuda.current_stream(grad_x.device).cuda_stream
         _check(load().atsfft_backward(self._h, grad_vals.shape[0], grad_vals.data_ptr(), ws.data_ptr(),
                                       grad_x.data_ptr(), s), "atsfft_backward")
@@ -291,3 +296,51 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def sparse_fft(x, plan: Plan):
+    """Differentiable transform of a batch x [batch, n] (or [batch, N, N]).
+
+    Returns (vals, locs, count, khat, status); vals [batch, max_out] carries
+    autograd through the value estimates at fixed located frequencies and
+    median choices (atsfft_backward); entries at or past count are zero.
+    """
+    return _SparseFFT.apply(x, plan)
+
+
+def _make_function():
+    import torch
+
+    class _SparseFFTFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, plan):
+            x = x.contiguous()
+            ws = torch.empty(plan.workspace_size(x.shape[0]), dtype=torch.uint8, device=x.device)
+            out = plan.execute_batched(x, ws=ws)
+            ctx.plan, ctx.ws = plan, ws
+            ctx.xshape, ctx.xdtype = x.shape, x.dtype
+            ctx.mark_non_differentiable(out["locs"], out["count"], out["khat"], out["status"])
+            return out["vals"], out["locs"], out["count"], out["khat"], out["status"]
+
+        @staticmethod
+        def backward(ctx, gvals, *unused):
+            gx = torch.empty(ctx.xshape, dtype=ctx.xdtype, device=ctx.ws.device)
+            if gvals is None:
+                gx.zero_()
+            else:
+                ctx.plan.backward(gvals.contiguous(), ctx.ws, gx)
+            return gx, None
+
+    return _SparseFFTFn
+
+
+class _Lazy:
+    _fn = None
+
+    def apply(self, *a):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_function()
+        return _Lazy._fn.apply(*a)
+
+
+_SparseFFT = _Lazy()

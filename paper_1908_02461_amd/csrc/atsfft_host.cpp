@@ -25,7 +25,7 @@ struct atsfft_plan_s {
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t *tab_dev;  // [96] element offsets by log2 B
-  size_t bucket_smem, est_smem;
+  size_t bucket_smem, est_smem, bwd_smem;
   uint32_t hash_parts;  // persistent hash workgroups per slab
   uint32_t slab_passes; // main-pass passes per signal
   uint32_t tile_slots;  // hash workgroups per slab and loop
@@ -171,6 +171,10 @@ Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
   off = align_up(off + (size_t)d.L_loc * l.jlist_loop, A);
   l.S = off;
   off = align_up(off + (size_t)d.max_out * 4, A);
+  l.tape = off;  // median loops of each located frequency (adjoint)
+  off = align_up(off + (size_t)d.max_out * 2, A);
+  l.bflag = off;
+  off = align_up(off + (size_t)kMaxLoops * 4, A);
   l.slice = off;
   l.total = off * (size_t)batch;
   return l;
@@ -191,6 +195,56 @@ void free_plan(atsfft_plan_s *p) {
   if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
   if (p->tab_dev) (void)hipFree(p->tab_dev);
   delete p;
+}
+
+KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_dev, int64_t *locs_dev,
+                    void *vals_dev, int32_t *count_dev, int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev) {
+  const atsfft_desc &d = plan->d;
+  KParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.seed = d.seed;
+  P.n = (uint32_t)d.n;
+  P.logn = plan->logn;
+  P.ndim = (uint32_t)d.ndim;
+  P.Bc_max = plan->Bc_max;
+  P.B0 = (uint32_t)d.B0;
+  P.B_max = (uint32_t)d.B_max;
+  P.alpha_probe = (uint32_t)d.alpha_probe;
+  P.alpha = (uint32_t)d.alpha;
+  P.L_loc = (uint32_t)d.L_loc;
+  P.L_est = (uint32_t)d.L_est;
+  P.T_vote = (uint32_t)d.T_vote;
+  P.P_max = (uint32_t)d.P_max;
+  P.d = (uint32_t)d.d;
+  P.gamma = (uint32_t)d.gamma;
+  P.max_out = (uint32_t)d.max_out;
+  P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
+  P.fixed_B = (uint32_t)d.fixed_B;
+  P.fixed_k = (uint32_t)d.fixed_k;
+  P.hash_parts = plan->hash_parts;
+  P.slab_passes = plan->slab_passes;
+  P.tile_slots = plan->tile_slots;
+  P.hash_loops = plan->hash_loops;
+  P.probe_levels = probe_levels(plan);
+  for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
+    P.probe_off[i] = i < P.probe_levels ? (uint64_t)kSlabs * probe_offset(plan, i) : 0;
+  P.q = d.q;
+  P.neg_log1mq = -std::log(1.0 - d.q);
+  P.noise_rate = d.noise_rate;
+  P.rho = d.rho;
+  P.G = plan->G_dev;
+  P.Ghat = plan->Ghat_dev;
+  P.tab = plan->tab_dev;
+  P.ws = static_cast<uint8_t *>(ws_dev);
+  P.lay = lay;
+  P.x = x_dev;
+  P.x_sig = d.ndim == 1 ? d.n : d.n * d.n;
+  P.locs = locs_dev;
+  P.vals = vals_dev;
+  P.count = count_dev;
+  P.khat = khat_dev;
+  P.status = sig_status_dev;
+  return P;
 }
 
 }  // namespace
@@ -316,6 +370,7 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     if (v == 1 || v == 2 || v == 4 || v == 8) p->slab_passes = (uint32_t)v;
   }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
+  p->bwd_smem = bwd_smem_bytes(d->dtype, p->Bc_max, (uint32_t)d->max_out);
   if (p->bucket_smem > prop.sharedMemPerBlock) {
     char msg[160];
     std::snprintf(msg, sizeof(msg), "B_max^ndim = %u needs %zu bytes of LDS, device has %zu", p->Bc_max,
@@ -389,7 +444,7 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
          hipMemcpy(p->Ghat_dev, ghat_all.data(), ghat_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   }
   ok = ok && hipMemcpy(p->tab_dev, tab.data(), 96 * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
-  ok = ok && prepare_kernels(d->dtype, d->ndim, p->bucket_smem, p->est_smem) == hipSuccess;
+  ok = ok && prepare_kernels(d->dtype, d->ndim, p->bucket_smem, p->est_smem, p->bwd_smem) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_plan(p);
@@ -416,51 +471,8 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
     return fail(ATSFFT_EINVAL, "null device pointer");
   const Layout lay = make_layout(plan, batch);
   if (ws_bytes < lay.total) return fail(ATSFFT_EINVAL, "workspace too small");
+  KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev);
   const atsfft_desc &d = plan->d;
-  KParams P;
-  std::memset(&P, 0, sizeof(P));
-  P.seed = d.seed;
-  P.n = (uint32_t)d.n;
-  P.logn = plan->logn;
-  P.ndim = (uint32_t)d.ndim;
-  P.Bc_max = plan->Bc_max;
-  P.B0 = (uint32_t)d.B0;
-  P.B_max = (uint32_t)d.B_max;
-  P.alpha_probe = (uint32_t)d.alpha_probe;
-  P.alpha = (uint32_t)d.alpha;
-  P.L_loc = (uint32_t)d.L_loc;
-  P.L_est = (uint32_t)d.L_est;
-  P.T_vote = (uint32_t)d.T_vote;
-  P.P_max = (uint32_t)d.P_max;
-  P.d = (uint32_t)d.d;
-  P.gamma = (uint32_t)d.gamma;
-  P.max_out = (uint32_t)d.max_out;
-  P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
-  P.fixed_B = (uint32_t)d.fixed_B;
-  P.fixed_k = (uint32_t)d.fixed_k;
-  P.hash_parts = plan->hash_parts;
-  P.slab_passes = plan->slab_passes;
-  P.tile_slots = plan->tile_slots;
-  P.hash_loops = plan->hash_loops;
-  P.probe_levels = probe_levels(plan);
-  for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
-    P.probe_off[i] = i < P.probe_levels ? (uint64_t)kSlabs * probe_offset(plan, i) : 0;
-  P.q = d.q;
-  P.neg_log1mq = -std::log(1.0 - d.q);
-  P.noise_rate = d.noise_rate;
-  P.rho = d.rho;
-  P.G = plan->G_dev;
-  P.Ghat = plan->Ghat_dev;
-  P.tab = plan->tab_dev;
-  P.ws = static_cast<uint8_t *>(ws_dev);
-  P.lay = lay;
-  P.x = x_dev;
-  P.x_sig = d.ndim == 1 ? d.n : d.n * d.n;
-  P.locs = locs_dev;
-  P.vals = vals_dev;
-  P.count = count_dev;
-  P.khat = khat_dev;
-  P.status = sig_status_dev;
   std::array<hipEvent_t, 6> *rec = nullptr;
   if (d.flags & ATSFFT_FLAG_PROFILE) {
     if (plan->prof_free.empty()) {
@@ -499,11 +511,16 @@ atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *loc
 
 atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *grad_vals_dev, const void *ws_dev,
                               void *grad_x_dev, hipStream_t stream) {
-  (void)stream;
   if (!plan) return fail(ATSFFT_EINVAL, "null plan");
   if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
   if (!grad_vals_dev || !ws_dev || !grad_x_dev) return fail(ATSFFT_EINVAL, "null device pointer");
-  return fail(ATSFFT_ENOTSUPPORTED, "the adjoint of value estimation is not provided by this build");
+  const Layout lay = make_layout(plan, batch);
+  KParams P = make_params(plan, lay, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, const_cast<void *>(ws_dev));
+  if (launch_backward(P, plan->d.dtype, batch, grad_vals_dev, grad_x_dev, stream) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  return ATSFFT_SUCCESS;
 }
 
 atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t signal, atsfft_trace *out,

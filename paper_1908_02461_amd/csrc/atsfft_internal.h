@@ -53,7 +53,7 @@ static_assert(sizeof(ProbeRec) == 32, "ProbeRec layout");
 struct Layout {
   size_t slice;
   size_t state, hist, yprobe, ymain, ymain_loop, tloc, jcount;
-  size_t jbits, jbits_loop, jlist, jlist_loop, S;
+  size_t jbits, jbits_loop, jlist, jlist_loop, S, tape, bflag;
   size_t total;
 };
 
@@ -93,7 +93,10 @@ typedef void (*StageMark)(void *ctx, int stage);
 hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s, StageMark mark, void *ctx);
 hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out,
                              hipStream_t s);
-hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem);
+hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem, size_t bwd_smem);
+hipError_t launch_backward(const KParams &P, int dtype, int batch, const void *grad_vals, void *grad_x,
+                           hipStream_t s);
+size_t bwd_smem_bytes(int dtype, uint32_t Bc_max, uint32_t max_out);
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
 size_t estimate_smem_bytes(uint32_t max_out);
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);

@@ -16,6 +16,8 @@
 // largest case and workgroups past a signal's actual extent exit at once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "atsfft_internal.h"
 
 namespace atsfft {
@@ -110,6 +112,12 @@ __device__ __forceinline__ int32_t *jlist_of(const KParams &P, uint32_t sig, uin
 }
 __device__ __forceinline__ uint32_t *S_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.S);
+}
+__device__ __forceinline__ int32_t *bflag_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<int32_t *>(slice_of(P, sig) + P.lay.bflag);
+}
+__device__ __forceinline__ uint16_t *tape_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<uint16_t *>(slice_of(P, sig) + P.lay.tape);
 }
 template <typename R>
 __device__ __forceinline__ const R *taps_of(const KParams &P, int which, uint32_t logB) {
@@ -894,6 +902,40 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
 
 // ---------------------------------------------------------- k_estimate ----
 
+// Bucket, phase and window factor of the estimator display for frequency f
+// in one estimation loop (draw words es[] = sigma1, tau1, sigma2, tau2):
+// e_l(f) = y_hat_l[h] omega^{phase} / g with omega = e^{-2 pi i / n}.
+template <typename R> struct EstTerm {
+  uint32_t h, phase;
+  R g;
+};
+
+template <typename R, int NDIM>
+__device__ __forceinline__ EstTerm<R> est_term(const uint32_t *es, uint32_t f, uint32_t n, uint32_t logn,
+                                               uint32_t logB, uint32_t logW, uint32_t c, const R *gh) {
+  const uint32_t mask = n - 1u;
+  EstTerm<R> t;
+  if (NDIM == 1) {
+    const uint32_t p = (es[0] * f) & mask;
+    t.h = ((p + c) & mask) >> logW;
+    const uint32_t dd = ((t.h << logW) - p) & mask;
+    const int o = dd > (n >> 1) ? (int)dd - (int)n : (int)dd;
+    t.g = gh[o + (int)c];
+    t.phase = (es[1] * f) & mask;
+  } else {
+    const uint32_t f1 = f >> logn, f2 = f & mask;
+    const uint32_t p1 = (es[0] * f1) & mask, p2 = (es[2] * f2) & mask;
+    const uint32_t h1 = ((p1 + c) & mask) >> logW, h2 = ((p2 + c) & mask) >> logW;
+    const uint32_t dd1 = ((h1 << logW) - p1) & mask, dd2 = ((h2 << logW) - p2) & mask;
+    const int o1 = dd1 > (n >> 1) ? (int)dd1 - (int)n : (int)dd1;
+    const int o2 = dd2 > (n >> 1) ? (int)dd2 - (int)n : (int)dd2;
+    t.g = gh[o1 + (int)c] * gh[o2 + (int)c];
+    t.h = (h1 << logB) | h2;
+    t.phase = ((es[1] * f1) + (es[3] * f2)) & mask;
+  }
+  return t;
+}
+
 template <typename R, int N> __device__ __forceinline__ void sort_net(R (&a)[N]) {
 #pragma unroll
   for (int k = 2; k <= N; k <<= 1) {
@@ -986,51 +1028,271 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   C *vals = reinterpret_cast<C *>(P.vals) + (int64_t)sig * P.max_out;
   const uint32_t Le = P.L_est;
 
+  uint32_t *Sg = S_of(P, sig);
+  uint16_t *tape = tape_of(P, sig);
   for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
     const uint32_t f = sS[i];
-    R re[ML], im[ML];
+    R re[ML], im[ML], re0[ML], im0[ML];
 #pragma unroll
     for (int l = 0; l < ML; ++l) {
       re[l] = (R)INFINITY;
       im[l] = (R)INFINITY;
       if ((uint32_t)l < Le) {
-        uint32_t h, phase;
-        R g;
-        if (NDIM == 1) {
-          const uint32_t p = (es[l][0] * f) & mask;
-          h = ((p + c) & mask) >> logW;
-          const uint32_t dd = ((h << logW) - p) & mask;
-          const int o = dd > (n >> 1) ? (int)dd - (int)n : (int)dd;
-          g = gh[o + (int)c];
-          phase = (es[l][1] * f) & mask;
-        } else {
-          const uint32_t f1 = f >> logn, f2 = f & mask;
-          const uint32_t p1 = (es[l][0] * f1) & mask, p2 = (es[l][2] * f2) & mask;
-          const uint32_t h1 = ((p1 + c) & mask) >> logW, h2 = ((p2 + c) & mask) >> logW;
-          const uint32_t dd1 = ((h1 << logW) - p1) & mask, dd2 = ((h2 << logW) - p2) & mask;
-          const int o1 = dd1 > (n >> 1) ? (int)dd1 - (int)n : (int)dd1;
-          const int o2 = dd2 > (n >> 1) ? (int)dd2 - (int)n : (int)dd2;
-          g = gh[o1 + (int)c] * gh[o2 + (int)c];
-          h = (h1 << logB) | h2;
-          phase = ((es[l][1] * f1) + (es[l][3] * f2)) & mask;
-        }
-        const C yv = ymain_of<C>(P, sig, P.L_loc + l)[h];
+        const EstTerm<R> t = est_term<R, NDIM>(es[l], f, n, logn, logB, logW, c, gh);
+        const C yv = ymain_of<C>(P, sig, P.L_loc + l)[t.h];
         R sn, cs;
-        sincos_pi(-(R)phase * two_over_n, &sn, &cs);
+        sincos_pi(-(R)t.phase * two_over_n, &sn, &cs);
         const R zr = yv.x * cs - yv.y * sn;
         const R zi = yv.x * sn + yv.y * cs;
-        re[l] = zr / g;
-        im[l] = zi / g;
+        re[l] = zr / t.g;
+        im[l] = zi / t.g;
       }
+      re0[l] = re[l];
+      im0[l] = im[l];
     }
     sort_net<R, ML>(re);
     sort_net<R, ML>(im);
-    locs[i] = (int64_t)f;
     C v;
     v.x = re[Le / 2];
     v.y = im[Le / 2];
+    // the loops whose estimates are the medians (the first on ties): the
+    // tape of the adjoint
+    uint32_t lre = 0, lim = 0;
+    bool fre = false, fim = false;
+#pragma unroll
+    for (int l = 0; l < ML; ++l) {
+      if (!fre && (uint32_t)l < Le && re0[l] == v.x) {
+        fre = true;
+        lre = (uint32_t)l;
+      }
+      if (!fim && (uint32_t)l < Le && im0[l] == v.y) {
+        fim = true;
+        lim = (uint32_t)l;
+      }
+    }
+    locs[i] = (int64_t)f;
     vals[i] = v;
+    Sg[i] = f;
+    tape[i] = (uint16_t)(lre | (lim << 8));
   }
+}
+
+// ------------------------------------------------------------ adjoint ----
+
+// Gradient of a real loss through the values at fixed located frequencies
+// and fixed median choices.  Given the decisions, each value is real-linear
+// in x: its real part is Re(e_{l_re}(f)) and its imaginary part Im(e_{l_im}(f))
+// with e_l(f) = sum_t K_t x[sigma_l t + tau_l], K_t = c_l(f) G_t omega_B^{h t},
+// c_l(f) = omega^{tau_l f} / G'(o).  With g_f = dL/dRe v_f + i dL/dIm v_f the
+// gradient (same convention) is, per estimation loop l,
+//   ytil_l[j] = sum over f with h_l(f) = j of conj(c_l(f)) (g_re [l = l_re(f)]
+//                                                         + i g_im [l = l_im(f)]),
+//   u_l = the unnormalised inverse B-point DFT of ytil_l,
+//   grad_x[sigma_l t + tau_l] += G_t u_l[t mod B],
+// and zero at addresses no estimation loop samples.
+
+template <typename R> __global__ void k_fill_zero(typename CT<R>::C *p, int64_t count) {
+  using C = typename CT<R>::C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    C z;
+    z.x = 0;
+    z.y = 0;
+    p[i] = z;
+  }
+}
+
+// One workgroup per (estimation loop, signal): the bucket cotangent, then
+// its inverse DFT in LDS.
+template <typename R, int NDIM>
+__global__ __launch_bounds__(kBucketThreads) void k_bwd_bucket(KParams P, const void *grad_vals) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t l = blockIdx.x, sig = blockIdx.y;
+  const SigState s = *state_of(P, sig);
+  int32_t *flag = bflag_of(P, sig);
+  const bool usable = !(s.status & (kSigEmpty | kSigTruncated)) && s.count > 0 && s.count <= P.max_out;
+  if (!usable) {
+    if (threadIdx.x == 0) flag[l] = 0;
+    return;
+  }
+  const uint32_t count = s.count;
+  const uint32_t B = (uint32_t)s.B_star, logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const uint32_t n = P.n, logn = P.logn;
+  const uint32_t logW = logn - logB, c = (1u << logW) >> 1;
+  const R *gh = ghat_of<R>(P, logB);
+  const R two_over_n = (R)2 / (R)n;
+  uint32_t es[4];
+  {
+    const Draw d0 = draw(P, sig, kPhaseEst, (int)l, 0);
+    es[0] = d0.sigma;
+    es[1] = d0.tau;
+    if (NDIM == 2) {
+      const Draw d1 = draw(P, sig, kPhaseEst, (int)l, 1);
+      es[2] = d1.sigma;
+      es[3] = d1.tau;
+    } else {
+      es[2] = es[3] = 0;
+    }
+  }
+  // ytil accumulated in LDS in natural order (collisions of located
+  // frequencies in one bucket add atomically), then conjugated into
+  // bit-reversed order so that a forward DFT gives the conjugate of the
+  // inverse one
+  C *buf = reinterpret_cast<C *>(smem);
+  R *bufr = reinterpret_cast<R *>(smem);
+  __shared__ uint32_t any;
+  if (threadIdx.x == 0) any = 0;
+  for (uint32_t b = threadIdx.x; b < Bc; b += blockDim.x) {
+    C z;
+    z.x = 0;
+    z.y = 0;
+    buf[b] = z;
+  }
+  __syncthreads();
+  const uint32_t *S = S_of(P, sig);
+  const uint16_t *tape = tape_of(P, sig);
+  const C *gv = reinterpret_cast<const C *>(grad_vals) + (int64_t)sig * P.max_out;
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+    const uint32_t tp = tape[i];
+    const bool on_re = (tp & 0xFFu) == l, on_im = (tp >> 8) == l;
+    if (!(on_re || on_im)) continue;
+    const EstTerm<R> t = est_term<R, NDIM>(es, S[i], n, logn, logB, logW, c, gh);
+    R sn, cs;
+    sincos_pi(-(R)t.phase * two_over_n, &sn, &cs);  // c_l(f) = (cs + i sn) / g
+    const C g = gv[i];
+    const R cr = on_re ? g.x : (R)0, ci = on_im ? g.y : (R)0;  // coefficient cr + i ci
+    // conj(c) (cr + i ci) = (cs - i sn)(cr + i ci) / g
+    atomicAdd(&bufr[2 * t.h], (cs * cr + sn * ci) / t.g);
+    atomicAdd(&bufr[2 * t.h + 1], (cs * ci - sn * cr) / t.g);
+    any = 1u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flag[l] = any ? 1 : 0;
+  if (!any) return;
+  {
+    C v[kBucketMaxPer];
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = threadIdx.x + (uint32_t)j * blockDim.x;
+      if (b < Bc) v[j] = buf[b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = threadIdx.x + (uint32_t)j * blockDim.x;
+      if (b < Bc) {
+        uint32_t dst;
+        if (NDIM == 1)
+          dst = bitrev(b, logB);
+        else
+          dst = (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
+        C w = v[j];
+        w.y = -w.y;
+        buf[dst] = w;
+      }
+    }
+  }
+  __syncthreads();
+  if (NDIM == 1) {
+    fft_axis<R>(buf, logB, 1, 0, 1);
+  } else {
+    fft_axis<R>(buf, logB, B, B, 1);
+    fft_axis<R>(buf, logB, B, 1, B);
+  }
+  C *u = ymain_of<C>(P, sig, P.L_loc + l) + P.Bc_max;  // slab-1 area: free after the forward
+  for (uint32_t b = threadIdx.x; b < Bc; b += blockDim.x) {
+    C v = buf[b];
+    v.y = -v.y;
+    u[b] = v;
+  }
+}
+
+// grad_x[sigma_l t + tau_l] += G_t u_l[t mod B] over the taps of every
+// estimation loop that carries a median; the same slab-per-XCD split as the
+// hash, so every address is updated from one XCD only.
+template <typename R, int NDIM>
+__global__ __launch_bounds__(kHashThreads) void k_bwd_scatter(KParams P, void *grad_x) {
+  using C = typename CT<R>::C;
+  const uint32_t slab = blockIdx.x % kSlabs;
+  const uint32_t slot = blockIdx.x / kSlabs;
+  const uint32_t nslots = gridDim.x / kSlabs;
+  const uint32_t l = blockIdx.y, sig = blockIdx.z;
+  if (!bflag_of(P, sig)[l]) return;
+  const SigState *st = state_of(P, sig);
+  const uint32_t B = (uint32_t)st->B_star;
+  const uint32_t logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  if (slot * kTile >= Bc) return;
+  const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t slab_shift = P.logn - 3;
+  const uint32_t w = min(P.alpha * B, n);
+  const uint32_t half = w >> 1;
+  const uint32_t wraps = w >> logB;
+  const R *G = taps_of<R>(P, 1, logB);
+  const C *u = ymain_of<C>(P, sig, P.L_loc + l) + P.Bc_max;
+  R *gx = reinterpret_cast<R *>(reinterpret_cast<C *>(grad_x) + (int64_t)sig * P.x_sig);
+  const Draw d0 = draw(P, sig, kPhaseEst, (int)l, 0);
+  const Draw d1 = NDIM == 2 ? draw(P, sig, kPhaseEst, (int)l, 1) : d0;
+  const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
+  for (uint32_t tile = slot; tile * kTile < Bc; tile += nslots) {
+    const uint32_t b = tile * kTile + bi;
+    if (b >= Bc) continue;
+    const C ub = u[b];
+    if (NDIM == 1) {
+      for (uint32_t r = g; r < wraps; r += 4) {
+        const uint32_t i = b + (r << logB);
+        const uint32_t a = (d0.sigma * (i - half) + d0.tau) & mask;
+        if ((a >> slab_shift) != slab) continue;
+        const R gt = G[i];
+        atomicAdd(&gx[2 * (size_t)a], gt * ub.x);
+        atomicAdd(&gx[2 * (size_t)a + 1], gt * ub.y);
+      }
+    } else {
+      const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
+      for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
+        const uint32_t i1 = b1 + (r1 << logB);
+        const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
+        if ((a1 >> slab_shift) != slab) continue;
+        const R g1 = G[i1];
+        for (uint32_t r2 = 0; r2 < wraps; ++r2) {
+          const uint32_t i2 = b2 + (r2 << logB);
+          const uint32_t a2 = (d1.sigma * (i2 - half) + d1.tau) & mask;
+          const R gg = g1 * G[i2];
+          const size_t a = (size_t)a1 * n + a2;
+          atomicAdd(&gx[2 * a], gg * ub.x);
+          atomicAdd(&gx[2 * a + 1], gg * ub.y);
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int NDIM>
+static hipError_t run_backward(const KParams &P, int batch, const void *grad_vals, void *grad_x, hipStream_t s) {
+  using C = typename CT<R>::C;
+  const int64_t total = (int64_t)batch * P.x_sig;
+  const int64_t zblocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_fill_zero<R>), dim3((uint32_t)zblocks), dim3(256), 0, s, reinterpret_cast<C *>(grad_x), total);
+  const size_t smem = bwd_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max, P.max_out);
+  hipLaunchKernelGGL((k_bwd_bucket<R, NDIM>), dim3(P.L_est, batch), dim3(kBucketThreads), smem, s, P, grad_vals);
+  const uint32_t slots = max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
+  hipLaunchKernelGGL((k_bwd_scatter<R, NDIM>), dim3(kSlabs * slots, P.L_est, batch), dim3(kHashThreads), 0, s, P,
+                     grad_x);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const KParams &P, int dtype, int batch, const void *grad_vals, void *grad_x, hipStream_t s) {
+  if (dtype == 0)
+    return P.ndim == 1 ? run_backward<float, 1>(P, batch, grad_vals, grad_x, s)
+                       : run_backward<float, 2>(P, batch, grad_vals, grad_x, s);
+  return P.ndim == 1 ? run_backward<double, 1>(P, batch, grad_vals, grad_x, s)
+                     : run_backward<double, 2>(P, batch, grad_vals, grad_x, s);
+}
+
+size_t bwd_smem_bytes(int dtype, uint32_t Bc_max, uint32_t max_out) {
+  (void)max_out;
+  return (dtype == 0 ? 8 : 16) * (size_t)Bc_max;
 }
 
 // ------------------------------------------------------- window tables ----
@@ -1088,9 +1350,12 @@ size_t estimate_smem_bytes(uint32_t max_out) {
   return 4 * (size_t)p2;
 }
 
-template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t est) {
+template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t est, size_t bwd) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bucket<R, NDIM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bucket);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_bucket<R, NDIM>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vote<NDIM>), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
@@ -1105,9 +1370,12 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
   return hipSuccess;
 }
 
-hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem) {
-  if (dtype == 0) return ndim == 1 ? set_smem<float, 1>(bucket_smem, est_smem) : set_smem<float, 2>(bucket_smem, est_smem);
-  return ndim == 1 ? set_smem<double, 1>(bucket_smem, est_smem) : set_smem<double, 2>(bucket_smem, est_smem);
+hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem, size_t bwd_smem) {
+  if (dtype == 0)
+    return ndim == 1 ? set_smem<float, 1>(bucket_smem, est_smem, bwd_smem)
+                     : set_smem<float, 2>(bucket_smem, est_smem, bwd_smem);
+  return ndim == 1 ? set_smem<double, 1>(bucket_smem, est_smem, bwd_smem)
+                   : set_smem<double, 2>(bucket_smem, est_smem, bwd_smem);
 }
 
 template <typename R, int NDIM>
