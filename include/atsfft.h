@@ -103,6 +103,9 @@ enum {
  *                and a relative floor rho * max |y_hat|^2.
  *   fixed_B, fixed_k     used with ATSFFT_FLAG_FIXED_B.
  *   max_batch    largest batch passed to atsfft_execute_batched.
+ *   n_min        0, or the shortest length (power of two) atsfft_execute_uneven
+ *                accepts; the plan then also holds tables for every power of
+ *                two in [n_min, n), with B0 and B_max clipped to each length.
  */
 typedef struct atsfft_desc {
   int32_t ndim;
@@ -128,6 +131,7 @@ typedef struct atsfft_desc {
   double rho;
   int64_t fixed_B;
   int64_t fixed_k;
+  int64_t n_min;
 } atsfft_desc;
 
 typedef struct atsfft_plan_s *atsfft_plan_t;
@@ -165,6 +169,29 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
                                      int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
                                      int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev,
                                      size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Algorithm 2 on `batch` signals of different lengths (powers of two in
+ * [n_min, n] of the plan; 2D: sides) packed in x_dev.  offsets and ns are
+ * HOST arrays [batch]: signal i starts at complex element offsets[i] of x_dev
+ * and has length ns[i] (2D: ns[i] x ns[i] elements).  Outputs are indexed by
+ * i exactly as for atsfft_execute_batched, and signal i draws its
+ * permutations with signal key i, so a signal gets the same result whatever
+ * else the batch holds.  Signals of one length run as one group (one launch
+ * sequence per distinct length).  The per-signal tables are staged through a
+ * plan-owned pinned buffer; a call waits for the previous call's upload.
+ * ws_dev must hold atsfft_workspace_size_uneven(plan, batch, ns) bytes.
+ * The adjoint and the trace read do not apply to uneven calls.
+ * Errors: ATSFFT_EINVAL (a length the plan does not cover, null pointers,
+ * workspace too small), ATSFFT_ENOMEM, ATSFFT_ELAUNCH.
+ */
+atsfft_status atsfft_execute_uneven(atsfft_plan_t plan, int32_t batch, const void *x_dev, const int64_t *offsets,
+                                    const int64_t *ns, int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
+                                    int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes,
+                                    hipStream_t stream);
+
+/* Workspace bytes of atsfft_execute_uneven for the lengths ns (host, [batch]). */
+atsfft_status atsfft_workspace_size_uneven(atsfft_plan_t plan, int32_t batch, const int64_t *ns, size_t *bytes);
 
 /* atsfft_execute_batched with batch = 1. */
 atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *locs_dev,

@@ -49,6 +49,7 @@ class Desc(C.Structure):
         ("rho", C.c_double),
         ("fixed_B", C.c_int64),
         ("fixed_k", C.c_int64),
+        ("n_min", C.c_int64),
     ]
 
 
@@ -75,6 +76,7 @@ EXPORTS = (
     "atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
     "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
     "atsfft_status_string", "atsfft_version", "atsfft_last_error", "atsfft_profile_read",
+    "atsfft_execute_uneven", "atsfft_workspace_size_uneven",
 )
 
 _lib = None
@@ -107,13 +109,16 @@ def load():
     L.atsfft_trace_read.argtypes = [vp, vp, C.c_int32, C.POINTER(Trace), vp]
     L.atsfft_destroy.argtypes = [vp]
     L.atsfft_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    I64P = C.POINTER(C.c_int64)
+    L.atsfft_execute_uneven.argtypes = [vp, C.c_int32, vp, I64P, I64P, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.atsfft_workspace_size_uneven.argtypes = [vp, C.c_int32, I64P, C.POINTER(sz)]
     L.atsfft_status_string.argtypes = [C.c_int]
     L.atsfft_status_string.restype = C.c_char_p
     L.atsfft_version.restype = C.c_char_p
     L.atsfft_last_error.restype = C.c_char_p
     for name in ("atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
                  "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
-                 "atsfft_profile_read"):
+                 "atsfft_profile_read", "atsfft_execute_uneven", "atsfft_workspace_size_uneven"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -206,6 +211,36 @@ class Plan:
             self._h, batch, x.data_ptr(), out["locs"].data_ptr(), out["vals"].data_ptr(),
             out["count"].data_ptr(), out["khat"].data_ptr(), out["status"].data_ptr(), ws.data_ptr(),
             ws.numel(), s), "atsfft_execute_batched")
+        out["ws"] = ws
+        return out
+
+    def execute_uneven(self, x, offsets, ns, out: Optional[dict] = None, ws=None, stream=None) -> dict:
+        """Signals of different lengths packed in the 1D device tensor x;
+        offsets and ns are sequences (host) of element offsets and lengths."""
+        import torch
+
+        if not x.is_cuda or x.dtype != self.torch_dtype or not x.is_contiguous():
+            raise ValueError("x must be a contiguous device tensor of the plan's complex dtype")
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        nsa = np.ascontiguousarray(ns, dtype=np.int64)
+        batch = int(nsa.size)
+        if offs.size != batch:
+            raise ValueError("offsets and ns must have the same length")
+        per = nsa if self.ndim == 1 else nsa * nsa
+        if np.any(offs + per > x.numel()):
+            raise ValueError("a signal runs past the end of x")
+        I64P = C.POINTER(C.c_int64)
+        b = C.c_size_t()
+        _check(load().atsfft_workspace_size_uneven(self._h, batch, nsa.ctypes.data_as(I64P), C.byref(b)),
+               "atsfft_workspace_size_uneven")
+        if ws is None or ws.numel() < b.value:
+            ws = torch.empty(b.value, dtype=torch.uint8, device=x.device)
+        out = out or self.outputs(batch, x.device)
+        s = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+        _check(load().atsfft_execute_uneven(
+            self._h, batch, x.data_ptr(), offs.ctypes.data_as(I64P), nsa.ctypes.data_as(I64P),
+            out["locs"].data_ptr(), out["vals"].data_ptr(), out["count"].data_ptr(), out["khat"].data_ptr(),
+            out["status"].data_ptr(), ws.data_ptr(), ws.numel(), s), "atsfft_execute_uneven")
         out["ws"] = ws
         return out
 

@@ -32,6 +32,12 @@ struct atsfft_plan_s {
   uint32_t hash_loops;  // main-pass loops per hash workgroup
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
+  // uneven batches: one plan per power-of-two length below n (index log2 n'),
+  // and a pinned staging buffer for the per-signal tables
+  atsfft_plan_s *sub[32];
+  void *stage_host;
+  size_t stage_bytes;
+  hipEvent_t stage_done;
 };
 
 namespace {
@@ -89,6 +95,8 @@ atsfft_status validate(const atsfft_desc *d) {
     return fail(ATSFFT_EINVAL, "2D N must be in [2^4, 2^15]");
   if (d->max_out < 1 || d->max_out > kMaxOut) return fail(ATSFFT_EINVAL, "max_out must be in [1, 16384]");
   if (d->max_batch < 1 || d->max_batch > 65535) return fail(ATSFFT_EINVAL, "max_batch must be in [1, 65535]");
+  if (d->n_min != 0 && (!is_pow2(d->n_min) || d->n_min > d->n || d->n_min < (d->ndim == 1 ? 64 : 16)))
+    return fail(ATSFFT_EINVAL, "n_min must be 0 or a power of two in [2^6 (2D: 2^4), n]");
   const int64_t Bmin = d->ndim == 1 ? 2 : 4;
   const bool fixed = (d->flags & ATSFFT_FLAG_FIXED_B) != 0;
   if (fixed) {
@@ -188,6 +196,10 @@ template <typename T> std::vector<T> convert(const std::vector<double> &v) {
 
 void free_plan(atsfft_plan_s *p) {
   if (!p) return;
+  for (atsfft_plan_s *q : p->sub)
+    if (q && q != p) free_plan(q);
+  if (p->stage_host) (void)hipHostFree(p->stage_host);
+  if (p->stage_done) (void)hipEventDestroy(p->stage_done);
   for (auto *pool : {&p->prof_used, &p->prof_free})
     for (auto &rec : *pool)
       for (hipEvent_t e : rec) (void)hipEventDestroy(e);
@@ -307,7 +319,7 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
   return ATSFFT_SUCCESS;
 }
 
-atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
+static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   if (!out) return fail(ATSFFT_EINVAL, "null plan pointer");
   *out = nullptr;
   atsfft_status st = validate(d);
@@ -454,6 +466,40 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   return ATSFFT_SUCCESS;
 }
 
+atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
+  atsfft_status st = create_plan(out, d);
+  if (st != ATSFFT_SUCCESS) return st;
+  atsfft_plan_s *p = *out;
+  p->sub[p->logn] = p;
+  if (d->n_min > 0 && d->n_min < d->n) {
+    // a plan for every shorter power-of-two length, with the same knobs
+    // clipped to that length
+    for (int64_t m = d->n_min; m < d->n; m *= 2) {
+      atsfft_desc e = *d;
+      e.n = m;
+      e.n_min = 0;
+      if (!(e.flags & ATSFFT_FLAG_FIXED_B)) {
+        const int64_t cap = m / e.alpha > 0 ? m / e.alpha : 1;
+        if (e.B_max > cap) e.B_max = cap;
+        const int64_t Bmin = e.ndim == 1 ? 2 : 4;
+        if (e.B_max < Bmin) e.B_max = Bmin;
+        if (e.B0 > e.B_max) e.B0 = e.B_max;
+      } else if (e.fixed_B > m / 2) {
+        e.fixed_B = m / 2;
+      }
+      atsfft_plan_t q = nullptr;
+      st = create_plan(&q, &e);
+      if (st != ATSFFT_SUCCESS) {
+        free_plan(p);
+        *out = nullptr;
+        return st;
+      }
+      p->sub[q->logn] = q;
+    }
+  }
+  return ATSFFT_SUCCESS;
+}
+
 atsfft_status atsfft_workspace_size(atsfft_plan_t plan, int32_t batch, size_t *bytes) {
   if (!plan || !bytes) return fail(ATSFFT_EINVAL, "null argument");
   if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
@@ -519,6 +565,111 @@ atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *gra
   if (launch_backward(P, plan->d.dtype, batch, grad_vals_dev, grad_x_dev, stream) != hipSuccess) {
     hipError_t e = hipGetLastError();
     return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  return ATSFFT_SUCCESS;
+}
+
+namespace {
+
+// Grouping of an uneven batch: signals of each length, in call order.
+struct Groups {
+  std::vector<std::vector<int32_t>> members;  // by log2 length
+  size_t header;                              // bytes of the per-signal tables
+  std::vector<size_t> base;                   // workspace offset of each group's slices
+  size_t total;
+};
+
+atsfft_status make_groups(const atsfft_plan_s *p, int32_t batch, const int64_t *ns, Groups &g) {
+  if (!ns) return fail(ATSFFT_EINVAL, "null ns");
+  if (batch < 1 || batch > p->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  g.members.assign(32, {});
+  for (int32_t i = 0; i < batch; ++i) {
+    const int64_t m = ns[i];
+    if (!is_pow2(m) || m > p->d.n) return fail(ATSFFT_EINVAL, "ns[i] must be a power of two the plan covers");
+    const uint32_t lg = ilog2_host((uint64_t)m);
+    if (!p->sub[lg]) return fail(ATSFFT_EINVAL, "ns[i] below the plan's n_min");
+    g.members[lg].push_back(i);
+  }
+  g.header = align_up((size_t)batch * 8, 256) + align_up((size_t)batch * 4, 256);
+  g.base.assign(32, 0);
+  size_t off = g.header;
+  for (uint32_t lg = 0; lg < 32; ++lg) {
+    if (g.members[lg].empty()) continue;
+    g.base[lg] = off;
+    off += make_layout(p->sub[lg], (int32_t)g.members[lg].size()).total;
+  }
+  g.total = off;
+  return ATSFFT_SUCCESS;
+}
+
+}  // namespace
+
+atsfft_status atsfft_workspace_size_uneven(atsfft_plan_t plan, int32_t batch, const int64_t *ns, size_t *bytes) {
+  if (!plan || !bytes) return fail(ATSFFT_EINVAL, "null argument");
+  Groups g;
+  atsfft_status st = make_groups(plan, batch, ns, g);
+  if (st != ATSFFT_SUCCESS) return st;
+  *bytes = g.total;
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_execute_uneven(atsfft_plan_t plan, int32_t batch, const void *x_dev, const int64_t *offsets,
+                                    const int64_t *ns, int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
+                                    int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes,
+                                    hipStream_t stream) {
+  if (!plan) return fail(ATSFFT_EINVAL, "null plan");
+  if (!x_dev || !offsets || !locs_dev || !vals_dev || !count_dev || !khat_dev || !sig_status_dev || !ws_dev)
+    return fail(ATSFFT_EINVAL, "null pointer");
+  Groups g;
+  atsfft_status st = make_groups(plan, batch, ns, g);
+  if (st != ATSFFT_SUCCESS) return st;
+  if (ws_bytes < g.total) return fail(ATSFFT_EINVAL, "workspace too small");
+  for (int32_t i = 0; i < batch; ++i)
+    if (offsets[i] < 0) return fail(ATSFFT_EINVAL, "negative offset");
+  // per-signal tables, group by group: input offsets, then call indices
+  if (!plan->stage_host || plan->stage_bytes < g.header) {
+    if (plan->stage_host) {
+      (void)hipEventSynchronize(plan->stage_done);
+      (void)hipHostFree(plan->stage_host);
+      plan->stage_host = nullptr;
+    }
+    if (hipHostMalloc(&plan->stage_host, g.header) != hipSuccess) return fail(ATSFFT_ENOMEM, "pinned staging allocation failed");
+    plan->stage_bytes = g.header;
+    if (!plan->stage_done && hipEventCreateWithFlags(&plan->stage_done, hipEventDisableTiming) != hipSuccess)
+      return fail(ATSFFT_ELAUNCH, "hipEventCreate failed");
+  } else if (plan->stage_done) {
+    (void)hipEventSynchronize(plan->stage_done);  // the previous upload has read the buffer
+  }
+  int64_t *h_off = static_cast<int64_t *>(plan->stage_host);
+  int32_t *h_map = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(plan->stage_host) + align_up((size_t)batch * 8, 256));
+  std::vector<int32_t> start(32, 0);
+  int32_t k = 0;
+  for (uint32_t lg = 0; lg < 32; ++lg) {
+    start[lg] = k;
+    for (int32_t i : g.members[lg]) {
+      h_off[k] = offsets[i];
+      h_map[k] = i;
+      ++k;
+    }
+  }
+  uint8_t *ws = static_cast<uint8_t *>(ws_dev);
+  if (hipMemcpyAsync(ws, plan->stage_host, g.header, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(plan->stage_done, stream) != hipSuccess)
+    return fail(ATSFFT_ELAUNCH, "table upload failed");
+  const int64_t *d_off = reinterpret_cast<const int64_t *>(ws);
+  const int32_t *d_map = reinterpret_cast<const int32_t *>(ws + align_up((size_t)batch * 8, 256));
+  for (uint32_t lg = 0; lg < 32; ++lg) {
+    const int32_t cnt = (int32_t)g.members[lg].size();
+    if (!cnt) continue;
+    const atsfft_plan_s *q = plan->sub[lg];
+    const Layout lay = make_layout(q, cnt);
+    KParams P = make_params(q, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws + g.base[lg]);
+    P.x_off = d_off + start[lg];
+    P.sig_map = d_map + start[lg];
+    if (launch_execute(P, q->d.dtype, cnt, stream, nullptr, nullptr) != hipSuccess) {
+      hipError_t e = hipGetLastError();
+      return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+    }
   }
   return ATSFFT_SUCCESS;
 }

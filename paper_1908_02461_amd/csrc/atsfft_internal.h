@@ -78,6 +78,8 @@ struct KParams {
   Layout lay;
   const void *x;
   int64_t x_sig;       // complex elements per signal
+  const int64_t *x_off;    // per-signal element offsets into x (device), or null: sig * x_sig
+  const int32_t *sig_map;  // per-signal index in the caller's batch (device), or null: sig
   int64_t *locs;
   void *vals;
   int32_t *count;

@@ -61,9 +61,12 @@ struct Draw {
 
 // One loop's permutation (Definition 1) for the key (signal, phase, iteration,
 // axis): sigma odd from the low word, tau from the high word, both mod n.
+// The signal key is the signal's index in the caller's batch (sig_map when a
+// call is split into groups of equal length).
 __device__ __forceinline__ Draw draw(const KParams &P, uint32_t sig, int phase, int iter, int axis) {
+  const uint64_t key = P.sig_map ? (uint64_t)P.sig_map[sig] : (uint64_t)sig;  // the signal's index in the call
   const uint64_t index =
-      ((((uint64_t)sig * 4ull + (uint64_t)phase) * 256ull + (uint64_t)iter) * 2ull) + (uint64_t)axis;
+      ((((uint64_t)key * 4ull + (uint64_t)phase) * 256ull + (uint64_t)iter) * 2ull) + (uint64_t)axis;
   const uint64_t r = splitmix64_at(P.seed, index);
   const uint32_t mask = P.n - 1u;
   Draw d;
@@ -85,6 +88,13 @@ __device__ __forceinline__ uint32_t inv_odd(uint32_t a) {
 
 __device__ __forceinline__ uint8_t *slice_of(const KParams &P, uint32_t sig) {
   return P.ws + (size_t)sig * P.lay.slice;
+}
+// element offset of a signal in the caller's input, and its output slot
+__device__ __forceinline__ int64_t x_offset(const KParams &P, uint32_t sig) {
+  return P.x_off ? P.x_off[sig] : (int64_t)sig * P.x_sig;
+}
+__device__ __forceinline__ int64_t out_slot(const KParams &P, uint32_t sig) {
+  return P.sig_map ? (int64_t)P.sig_map[sig] : (int64_t)sig;
 }
 __device__ __forceinline__ SigState *state_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<SigState *>(slice_of(P, sig) + P.lay.state);
@@ -337,7 +347,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
   const uint32_t half = w >> 1;
   const uint32_t wraps = w >> logB;
   const R *G = taps_of<R>(P, main_phase ? 1 : 0, logB);
-  const C *x = reinterpret_cast<const C *>(P.x) + (int64_t)sig * P.x_sig;
+  const C *x = reinterpret_cast<const C *>(P.x) + x_offset(P, sig);
   const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
   __shared__ R red_x[LG][4][kTile], red_y[LG][4][kTile];
 
@@ -976,9 +986,10 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   const uint32_t count = empty ? 0u : s.count;
   if (!empty && count > P.max_out) status |= kSigTruncated;
   if (threadIdx.x == 0) {
-    P.khat[sig] = s.khat;
-    P.count[sig] = (int32_t)count;
-    P.status[sig] = status;
+    const int64_t slot = out_slot(P, sig);
+    P.khat[slot] = s.khat;
+    P.count[slot] = (int32_t)count;
+    P.status[slot] = status;
     st->status = status;
   }
   if (empty || count > P.max_out || count == 0) return;
@@ -1024,8 +1035,8 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   const uint32_t logW = logn - logB, c = (1u << logW) >> 1;
   const R *gh = ghat_of<R>(P, logB);
   const R two_over_n = (R)2 / (R)n;
-  int64_t *locs = P.locs + (int64_t)sig * P.max_out;
-  C *vals = reinterpret_cast<C *>(P.vals) + (int64_t)sig * P.max_out;
+  int64_t *locs = P.locs + out_slot(P, sig) * P.max_out;
+  C *vals = reinterpret_cast<C *>(P.vals) + out_slot(P, sig) * P.max_out;
   const uint32_t Le = P.L_est;
 
   uint32_t *Sg = S_of(P, sig);
