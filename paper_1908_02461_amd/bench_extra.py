@@ -1,0 +1,174 @@
+"""Benchmarks of the workloads beyond the headline one (bench.py --workload):
+the 2D image workload, the uneven batch, and forward + adjoint.  Each returns
+one JSON-serialisable record."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def _timed(fn, steps):
+    import torch
+
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _base(metric, value, unit, args, ms, config, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_c3(args):
+    """2D: 4096 x 4096 c64 images, k = 256 log-uniform [0.1, 1], 30 dB."""
+    import torch
+
+    from paper_1908_02461_amd import atsfft as A
+    from paper_1908_02461_amd import synth
+
+    N, k, batch = 4096, 256, 8
+    _log(f"generating {batch} images")
+    imgs = [synth.make("c3_2d_c64_n4096_k256_snr30", 2000 + i) for i in range(batch)]
+    x = torch.from_numpy(np.stack([t[0] for t in imgs])).cuda()
+    plan = A.Plan(2, N, "c64", seed=7, max_batch=batch)
+    out = plan.outputs(batch, x.device)
+    ws = plan.workspace(batch, x.device)
+    step = lambda: plan.execute_batched(x, out=out, ws=ws)
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(step, args.steps)
+    y = torch.empty_like(x)
+    dense = lambda: torch.fft.fft2(x, out=y)
+    for _ in range(args.warmup):
+        dense()
+    ms_dense = _timed(dense, args.steps)
+    rec = []
+    for i in range(batch):
+        r = plan.results(out, i)
+        rec.append(float(np.mean(np.isin(imgs[i][1], r["locs"]))))
+    line = _base("sparse 2D transforms/sec and speedup vs same-GPU dense FFT2 at 4096^2, k=256",
+                 batch / (ms / 1e3), "transforms/s", args, ms,
+                 {"workload": "c3_2d_c64_n4096_k256_snr30", "N": N, "k": k, "batch": batch})
+    line.update({"dense_fft2_ms_per_transform": ms_dense / batch, "speedup_vs_dense_fft2": ms_dense / ms,
+                 "recovered_fraction": float(np.mean(rec)),
+                 "B_star": sorted({plan.trace(ws, i, full=False)["B_star"] for i in range(batch)})})
+    return line
+
+
+def run_c4(args):
+    """512 c64 signals, n uniform over 2^16..2^22, k log-uniform [4, 1024],
+    SNR uniform [20, 60] dB, magnitudes uniform [0.5, 1]; one uneven call."""
+    import torch
+
+    from paper_1908_02461_amd import atsfft as A
+    from paper_1908_02461_amd import synth
+
+    batch = 512
+    rng = np.random.Generator(np.random.PCG64(4242))
+    ns = (1 << rng.integers(16, 23, size=batch)).astype(np.int64)
+    ks = np.rint(np.exp(rng.uniform(np.log(4), np.log(1024), size=batch))).astype(np.int64)
+    snrs = rng.uniform(20.0, 60.0, size=batch)
+    offs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    total = int(ns.sum())
+    _log(f"generating {batch} signals, {total * 8 / 2**30:.2f} GiB")
+    x = torch.empty(total, dtype=torch.complex64, device="cuda")
+    planted = []
+    for i in range(batch):
+        xi, locs, _ = synth.planted_1d_device(int(ns[i]), int(ks[i]), 3000 + i, mag=("uniform", 0.5, 1.0),
+                                              snr_db=float(snrs[i]))
+        x[offs[i]:offs[i] + ns[i]] = xi
+        planted.append(locs)
+        if (i + 1) % 128 == 0:
+            _log(f"  {i + 1}/{batch}")
+    plan = A.Plan(1, 1 << 22, "c64", seed=11, n_min=1 << 16, max_batch=batch)
+    out = plan.outputs(batch, x.device)
+    step = lambda: plan.execute_uneven(x, offs, ns, out=out)
+    o = step()
+    ws = o["ws"]
+    step = lambda: plan.execute_uneven(x, offs, ns, out=out, ws=ws)
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(step, args.steps)
+    # dense FFT of every signal, grouped by length
+    groups = {}
+    for i, m in enumerate(ns):
+        groups.setdefault(int(m), []).append(i)
+    views = {m: torch.stack([x[offs[i]:offs[i] + m] for i in idx]) for m, idx in groups.items()}
+    outs = {m: torch.empty_like(v) for m, v in views.items()}
+
+    def dense():
+        for m, v in views.items():
+            torch.fft.fft(v, dim=-1, out=outs[m])
+
+    for _ in range(args.warmup):
+        dense()
+    ms_dense = _timed(dense, args.steps)
+    rec, sat = [], 0
+    for i in range(batch):
+        r = plan.results(out, i)
+        rec.append(float(np.mean(np.isin(planted[i], r["locs"]))))
+        sat += bool(r["status"] & A.SIG_PROBE_SATURATED)
+    line = _base("sparse transforms/sec, uneven batch of 512 (n 2^16..2^22, k 4..1024)", batch / (ms / 1e3),
+                 "transforms/s", args, ms,
+                 {"workload": "c4_1d_c64_uneven_b512", "batch": batch, "n_range": [1 << 16, 1 << 22],
+                  "k_range": [4, 1024], "snr_db_range": [20, 60], "total_gib": total * 8 / 2**30})
+    line.update({"dense_fft_ms_per_batch": ms_dense, "speedup_vs_dense_fft": ms_dense / ms,
+                 "recovered_fraction": float(np.mean(rec)), "probe_saturated": sat})
+    return line
+
+
+def run_c5(args):
+    """Forward + adjoint: batch 64 of c64 n = 2^20, k = 128, 40 dB; loss =
+    sum |X_hat(located) - target|^2 with random complex targets."""
+    import torch
+
+    from paper_1908_02461_amd import atsfft as A
+    from paper_1908_02461_amd import synth
+
+    n, k, batch = 1 << 20, 128, 64
+    _log(f"generating {batch} signals n={n}")
+    x = torch.stack([synth.planted_1d_device(n, k, 5000 + i, mag=("uniform", 0.5, 1.0), snr_db=40.0)[0]
+                     for i in range(batch)]).contiguous()
+    plan = A.Plan(1, n, "c64", seed=13, max_batch=batch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    targets = torch.randn((batch, plan.max_out), generator=g, device="cuda", dtype=torch.complex64)
+    xr = x.clone().requires_grad_(True)
+
+    def step():
+        xr.grad = None
+        vals, locs, count, khat, status = A.sparse_fft(xr, plan)
+        mask = torch.arange(plan.max_out, device="cuda")[None, :] < count[:, None]
+        loss = torch.sum(torch.abs(vals - targets) ** 2 * mask)
+        loss.backward()
+
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(step, args.steps)
+    fwd = lambda: plan.execute_batched(x)
+    for _ in range(args.warmup):
+        fwd()
+    ms_fwd = _timed(fwd, args.steps)
+    line = _base("forward+adjoint transforms/sec at n=2^20, k=128 (loss over located values)",
+                 batch / (ms / 1e3), "transforms/s", args, ms,
+                 {"workload": "c5_1d_c64_n1m_k128_snr40_grad", "n": n, "k": k, "batch": batch})
+    line.update({"forward_only_ms_per_step": ms_fwd, "adjoint_share": 1.0 - ms_fwd / ms})
+    return line
+
+
+def run(args):
+    return {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)

@@ -76,3 +76,24 @@ def make(workload: str, seed: int):
     dt = np.complex64 if w["dtype"] == "c64" else np.complex128
     fn = planted_1d if w["ndim"] == 1 else planted_2d
     return fn(w["n"], w["k"], seed, mag=w["mag"], snr_db=w["snr_db"], dtype=dt)
+
+
+def planted_1d_device(n: int, k: int, seed: int, mag=None, snr_db=None, device="cuda"):
+    """planted_1d built on the GPU (complex64) for large benchmark batches:
+    the same recipe, with the inverse DFT and the noise drawn by torch."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    locs = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+    amps = _magnitudes(rng, k, mag) * np.exp(1j * rng.uniform(0.0, 2 * np.pi, size=k))
+    X = torch.zeros(n, dtype=torch.complex64, device=device)
+    X[torch.from_numpy(locs).to(device)] = torch.from_numpy(amps.astype(np.complex64)).to(device)
+    x = torch.fft.ifft(X)
+    if snr_db is not None:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+        p_sig = float(torch.mean(torch.abs(x) ** 2))
+        scale = float(np.sqrt(p_sig / (10.0 ** (snr_db / 10.0)) / 2.0))
+        noise = torch.randn(n, generator=g, device=device) + 1j * torch.randn(n, generator=g, device=device)
+        x = x + (noise * scale).to(torch.complex64)
+    return x, locs, amps
