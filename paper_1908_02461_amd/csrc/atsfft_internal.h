@@ -15,6 +15,8 @@ constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap grou
 constexpr int kSlabs = 8;            // address slabs of a signal, one per XCD
 constexpr int kVoteThreads = 256;
 constexpr int kEstThreads = 256;
+constexpr int kGatherThreads = 256;  // adjoint gather: threads per block
+constexpr int kGatherPer = 4;        // addresses per thread and pass
 constexpr int kMaxOut = 16384;
 
 enum : uint32_t {

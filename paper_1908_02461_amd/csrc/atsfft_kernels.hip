@@ -1102,16 +1102,6 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
 //   grad_x[sigma_l t + tau_l] += G_t u_l[t mod B],
 // and zero at addresses no estimation loop samples.
 
-template <typename R> __global__ void k_fill_zero(typename CT<R>::C *p, int64_t count) {
-  using C = typename CT<R>::C;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    C z;
-    z.x = 0;
-    z.y = 0;
-    p[i] = z;
-  }
-}
-
 // One workgroup per (estimation loop, signal): the bucket cotangent, then
 // its inverse DFT in LDS.
 template <typename R, int NDIM>
@@ -1219,61 +1209,87 @@ __global__ __launch_bounds__(kBucketThreads) void k_bwd_bucket(KParams P, const 
   }
 }
 
-// grad_x[sigma_l t + tau_l] += G_t u_l[t mod B] over the taps of every
-// estimation loop that carries a median; the same slab-per-XCD split as the
-// hash, so every address is updated from one XCD only.
+// The scatter grad_x[sigma_l t + tau_l] += G_t u_l[t mod B], done as a gather:
+// within one loop t -> sigma_l t + tau_l is a bijection of Z_n (sigma_l odd),
+// so address a is reached by the single tap t = sigma_l^{-1} (a - tau_l) at
+// most, and only when t lies in the window.  Each thread owns kGatherPer
+// addresses, sums its loops in index order and writes every address once,
+// zero included: no atomics, no separate clearing pass, and the same result
+// on every run.  For 2D the tap test splits per axis (row, then column).
 template <typename R, int NDIM>
-__global__ __launch_bounds__(kHashThreads) void k_bwd_scatter(KParams P, void *grad_x) {
+__global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *grad_x) {
   using C = typename CT<R>::C;
-  const uint32_t slab = blockIdx.x % kSlabs;
-  const uint32_t slot = blockIdx.x / kSlabs;
-  const uint32_t nslots = gridDim.x / kSlabs;
-  const uint32_t l = blockIdx.y, sig = blockIdx.z;
-  if (!bflag_of(P, sig)[l]) return;
-  const SigState *st = state_of(P, sig);
-  const uint32_t B = (uint32_t)st->B_star;
-  const uint32_t logB = ilog2(B);
-  const uint32_t Bc = NDIM == 1 ? B : B * B;
-  if (slot * kTile >= Bc) return;
-  const uint32_t n = P.n, mask = n - 1u;
-  const uint32_t slab_shift = P.logn - 3;
-  const uint32_t w = min(P.alpha * B, n);
-  const uint32_t half = w >> 1;
-  const uint32_t wraps = w >> logB;
-  const R *G = taps_of<R>(P, 1, logB);
-  const C *u = ymain_of<C>(P, sig, P.L_loc + l) + P.Bc_max;
-  R *gx = reinterpret_cast<R *>(reinterpret_cast<C *>(grad_x) + (int64_t)sig * P.x_sig);
-  const Draw d0 = draw(P, sig, kPhaseEst, (int)l, 0);
-  const Draw d1 = NDIM == 2 ? draw(P, sig, kPhaseEst, (int)l, 1) : d0;
-  const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
-  for (uint32_t tile = slot; tile * kTile < Bc; tile += nslots) {
-    const uint32_t b = tile * kTile + bi;
-    if (b >= Bc) continue;
-    const C ub = u[b];
-    if (NDIM == 1) {
-      for (uint32_t r = g; r < wraps; r += 4) {
-        const uint32_t i = b + (r << logB);
-        const uint32_t a = (d0.sigma * (i - half) + d0.tau) & mask;
-        if ((a >> slab_shift) != slab) continue;
-        const R gt = G[i];
-        atomicAdd(&gx[2 * (size_t)a], gt * ub.x);
-        atomicAdd(&gx[2 * (size_t)a + 1], gt * ub.y);
+  const uint32_t sig = blockIdx.y;
+  __shared__ uint32_t s_inv[kMaxLoops][NDIM], s_tau[kMaxLoops][NDIM];
+  __shared__ const C *s_u[kMaxLoops];
+  __shared__ uint32_t s_nl;
+  const int32_t *flag = bflag_of(P, sig);
+  if (threadIdx.x == 0) {
+    uint32_t nl = 0;
+    for (uint32_t l = 0; l < P.L_est; ++l) {
+      if (!flag[l]) continue;
+      for (int ax = 0; ax < NDIM; ++ax) {
+        const Draw d = draw(P, sig, kPhaseEst, (int)l, ax);
+        s_inv[nl][ax] = inv_odd(d.sigma);
+        s_tau[nl][ax] = d.tau;
       }
-    } else {
-      const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
-      for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
-        const uint32_t i1 = b1 + (r1 << logB);
-        const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
-        if ((a1 >> slab_shift) != slab) continue;
-        const R g1 = G[i1];
-        for (uint32_t r2 = 0; r2 < wraps; ++r2) {
-          const uint32_t i2 = b2 + (r2 << logB);
-          const uint32_t a2 = (d1.sigma * (i2 - half) + d1.tau) & mask;
-          const R gg = g1 * G[i2];
-          const size_t a = (size_t)a1 * n + a2;
-          atomicAdd(&gx[2 * a], gg * ub.x);
-          atomicAdd(&gx[2 * a + 1], gg * ub.y);
+      s_u[nl] = ymain_of<C>(P, sig, P.L_loc + l) + P.Bc_max;
+      ++nl;
+    }
+    s_nl = nl;
+  }
+  __syncthreads();
+  const uint32_t nl = s_nl;
+  const uint32_t B = (uint32_t)state_of(P, sig)->B_star;
+  const uint32_t logB = ilog2(B);
+  const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t w = min(P.alpha * B, n), half = w >> 1;
+  const R *G = nl ? taps_of<R>(P, 1, logB) : nullptr;
+  C *gx = reinterpret_cast<C *>(grad_x) + (int64_t)sig * P.x_sig;
+  const uint32_t total = (uint32_t)P.x_sig;
+  const uint32_t span = kGatherThreads * kGatherPer;
+  for (uint32_t base = blockIdx.x * span; base < total; base += gridDim.x * span) {
+    R acc_re[kGatherPer], acc_im[kGatherPer];
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j) acc_re[j] = acc_im[j] = (R)0;
+    for (uint32_t q = 0; q < nl; ++q) {
+      const C *u = s_u[q];
+      if (NDIM == 1) {
+#pragma unroll
+        for (int j = 0; j < kGatherPer; ++j) {
+          const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
+          const uint32_t i = (s_inv[q][0] * (a - s_tau[q][0]) + half) & mask;
+          if (i < w) {
+            const R g = G[i];
+            const C v = u[i & (B - 1u)];
+            acc_re[j] += g * v.x;
+            acc_im[j] += g * v.y;
+          }
         }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kGatherPer; ++j) {
+          const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
+          const uint32_t a1 = a >> P.logn, a2 = a & mask;
+          const uint32_t i1 = (s_inv[q][0] * (a1 - s_tau[q][0]) + half) & mask;
+          if (i1 >= w) continue;
+          const uint32_t i2 = (s_inv[q][1] * (a2 - s_tau[q][1]) + half) & mask;
+          if (i2 >= w) continue;
+          const R g = G[i1] * G[i2];
+          const C v = u[((i1 & (B - 1u)) << logB) | (i2 & (B - 1u))];
+          acc_re[j] += g * v.x;
+          acc_im[j] += g * v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j) {
+      const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
+      if (a < total) {
+        C o;
+        o.x = acc_re[j];
+        o.y = acc_im[j];
+        gx[a] = o;
       }
     }
   }
@@ -1281,15 +1297,11 @@ __global__ __launch_bounds__(kHashThreads) void k_bwd_scatter(KParams P, void *g
 
 template <typename R, int NDIM>
 static hipError_t run_backward(const KParams &P, int batch, const void *grad_vals, void *grad_x, hipStream_t s) {
-  using C = typename CT<R>::C;
-  const int64_t total = (int64_t)batch * P.x_sig;
-  const int64_t zblocks = std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_fill_zero<R>), dim3((uint32_t)zblocks), dim3(256), 0, s, reinterpret_cast<C *>(grad_x), total);
   const size_t smem = bwd_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max, P.max_out);
   hipLaunchKernelGGL((k_bwd_bucket<R, NDIM>), dim3(P.L_est, batch), dim3(kBucketThreads), smem, s, P, grad_vals);
-  const uint32_t slots = max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
-  hipLaunchKernelGGL((k_bwd_scatter<R, NDIM>), dim3(kSlabs * slots, P.L_est, batch), dim3(kHashThreads), 0, s, P,
-                     grad_x);
+  const uint32_t span = kGatherThreads * kGatherPer;
+  const uint32_t blocks = (uint32_t)std::min<int64_t>((P.x_sig + span - 1) / span, 1024);
+  hipLaunchKernelGGL((k_bwd_gather<R, NDIM>), dim3(blocks, batch), dim3(kGatherThreads), 0, s, P, grad_x);
   return hipGetLastError();
 }
 
