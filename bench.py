@@ -120,13 +120,14 @@ def main():
     ap.add_argument("--no-per-signal", action="store_true", help="skip the plain per-signal form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5", "known_k"),
                     help="c2: 1D n=2^22 k=64 (default); c3: 2D 4096^2 k=256; c4: uneven batch of 512; "
-                         "c5: forward + adjoint, batch 64 of n=2^20 k=128")
+                         "c5: forward + adjoint, batch 64 of n=2^20 k=128; "
+                         "known_k: ATSFFT against the known-k form of Algorithm 1")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the transform of one signal does not span GPUs "
-              "and this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+              "and the library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload != "c2":

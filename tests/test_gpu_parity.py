@@ -98,6 +98,23 @@ def test_fixed_bucket_count(A):
     _check_batch(A, plan, [x], "fixed B")
 
 
+@pytest.mark.parametrize("ndim,n,k,dt,snr", [(1, 1 << 16, 16, "c128", None), (1, 1 << 16, 16, "c64", 30.0),
+                                              (2, 256, 4, "c128", None)])
+def test_known_k_form_at_sqrt_nk(A, ndim, n, k, dt, snr):
+    """The known-k sparse FFT the paper compares against (Algorithm 1, the
+    bucket count B = sqrt(n k) per axis, num = d k): 1D n = 2^16, k = 16 gives
+    B = 1024; 2D N = 256, k = 4 gives 32 per axis."""
+    B = int(round(np.sqrt(n * k)))
+    assert B & (B - 1) == 0
+    plan = A.Plan(ndim, n, dt, seed=5, max_batch=2, fixed_B=B, fixed_k=k)
+    npdt = np.complex64 if dt == "c64" else np.complex128
+    make = synth.planted_1d if ndim == 1 else synth.planted_2d
+    xs = [make(n, k, 60 + i, mag=("uniform", 0.5, 1.0), snr_db=snr, dtype=npdt)[0] for i in range(2)]
+    out, _ = _check_batch(A, plan, xs, f"known-k {ndim}D {dt}")
+    for i in range(2):
+        assert plan.results(out, i)["khat"] == k
+
+
 def test_zero_signal_is_empty(A):
     n = 1 << 12
     plan = A.Plan(1, n, "c64", seed=1, max_batch=2, B_max=64)
