@@ -26,10 +26,10 @@ struct atsfft_plan_s {
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t *tab_dev;  // [96] element offsets by log2 B
   size_t bucket_smem, est_smem, bwd_smem;
-  uint32_t hash_parts;  // persistent hash workgroups per slab
-  uint32_t slab_passes; // main-pass passes per signal
   uint32_t tile_slots;  // hash workgroups per slab and loop
   uint32_t hash_loops;  // main-pass loops per hash workgroup
+  uint32_t probe_first; // first probe round covers B up to this
+  uint32_t probe_step;  // probe levels per later round
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
   // uneven batches: one plan per power-of-two length below n (index log2 n'),
@@ -233,8 +233,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
   P.fixed_B = (uint32_t)d.fixed_B;
   P.fixed_k = (uint32_t)d.fixed_k;
-  P.hash_parts = plan->hash_parts;
-  P.slab_passes = plan->slab_passes;
+  P.probe_first = plan->probe_first;
+  P.probe_step = plan->probe_step;
   P.tile_slots = plan->tile_slots;
   P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
@@ -353,20 +353,6 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
   p->Bc_max = (uint32_t)(d->ndim == 1 ? Bbig : Bbig * Bbig);
   p->bucket_smem = bucket_smem_bytes(d->dtype, p->Bc_max);
-  // persistent main-pass hash grid: kSlabs * hash_parts workgroups, two per
-  // CU, all resident at once so that they walk the batch together
-  p->hash_parts = (uint32_t)std::max(1, prop.multiProcessorCount * 2 / kSlabs);
-  if (const char *env = std::getenv("ATSFFT_HASH_PARTS")) {
-    const long v = std::strtol(env, nullptr, 10);
-    if (v >= 1 && v <= 4096) p->hash_parts = (uint32_t)v;
-  }
-  // passes per signal in the main pass: a slab of at most 2 MiB per XCD
-  {
-    const int64_t sig_bytes = (d->ndim == 1 ? n : n * n) * (d->dtype == ATSFFT_C64 ? 8 : 16);
-    uint32_t passes = 1;
-    while (passes < 8 && sig_bytes / (kSlabs * (int64_t)passes) > ((int64_t)2 << 20)) passes *= 2;
-    p->slab_passes = passes;
-  }
   p->hash_loops = 1;
   if (const char *env = std::getenv("ATSFFT_HASH_LOOPS")) {
     const long v = std::strtol(env, nullptr, 10);
@@ -377,9 +363,15 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->tile_slots = (uint32_t)v;
   }
-  if (const char *env = std::getenv("ATSFFT_SLAB_PASSES")) {
+  p->probe_first = 2048;
+  if (const char *env = std::getenv("ATSFFT_PROBE_FIRST")) {
     const long v = std::strtol(env, nullptr, 10);
-    if (v == 1 || v == 2 || v == 4 || v == 8) p->slab_passes = (uint32_t)v;
+    if (v >= 1 && v <= (1 << 20)) p->probe_first = (uint32_t)v;
+  }
+  p->probe_step = 2;
+  if (const char *env = std::getenv("ATSFFT_PROBE_STEP")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 32) p->probe_step = (uint32_t)v;
   }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
   p->bwd_smem = bwd_smem_bytes(d->dtype, p->Bc_max, (uint32_t)d->max_out);

@@ -66,10 +66,10 @@ struct KParams {
   uint32_t B0, B_max, alpha_probe, alpha;
   uint32_t L_loc, L_est, T_vote, P_max, d, gamma, max_out, fixed;
   uint32_t fixed_B, fixed_k;
-  uint32_t hash_parts;  // persistent hash grid: kSlabs * hash_parts workgroups
-  uint32_t slab_passes; // main-pass passes per signal (power of two)
   uint32_t tile_slots;  // hash tile slots per slab
   uint32_t hash_loops;  // main-pass loops per hash workgroup (1D: 1..3)
+  uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
+  uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
   uint64_t probe_off[kMaxProbe];       // complex offset of level i's bucket arrays in the probe area
   double q, neg_log1mq, noise_rate, rho;

@@ -1409,13 +1409,13 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   if (mark) mark(ctx, 0);
   hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
   if (!P.fixed) {
-    // rounds of probe levels: every level up to B = 2048 at once, then two
-    // levels per round
+    // rounds of probe levels: every level up to B = probe_first at once, then
+    // probe_step levels per round
     uint32_t lo = 0;
     while (lo < P.probe_levels) {
-      uint32_t hi = lo == 0 ? 1 : lo + 2;
+      uint32_t hi = lo == 0 ? 1 : lo + P.probe_step;
       if (lo == 0)
-        while (hi < P.probe_levels && (P.B0 << hi) <= 2048u) ++hi;
+        while (hi < P.probe_levels && (P.B0 << hi) <= P.probe_first) ++hi;
       hi = min(hi, P.probe_levels);
       const uint32_t Bt = P.B0 << (hi - 1);
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
