@@ -92,6 +92,50 @@ def measured_traffic(batch):
         return None
 
 
+MASK64 = (1 << 64) - 1
+
+
+def _splitmix64_at(seed, index):
+    """SplitMix64 output at a counter index (the library's draw generator)."""
+    z = (seed + (index + 1) * 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def _loop_lines(seed, sig, phase, it, n, w):
+    """128-byte lines of c64 samples one 1D loop reads: x[(sigma t + tau) mod n],
+    t in [-w/2, w/2), with (sigma, tau) drawn as the library documents."""
+    r = _splitmix64_at(seed, ((sig * 4 + phase) * 256 + it) * 2)
+    sigma, tau = (r % n) | 1, (r >> 32) % n
+    t = np.arange(w, dtype=np.int64) - w // 2
+    return ((sigma * t + tau) % n) >> 4
+
+
+def touched_bytes(desc, trs):
+    """Distinct 128-byte lines of the input (times 128) plus the bucket values
+    written, per batch: for the main-loop hash launch, and for the whole step
+    (probe levels the trace shows, plus the main loops)."""
+    from paper_1908_02461_amd import atsfft as A
+
+    n, L = desc.n, desc.L_loc + desc.L_est
+    main = step = 0
+    for s, t in enumerate(trs):
+        if t["status"] & A.SIG_EMPTY:  # no main loops
+            continue
+        B = t["B_star"]
+        w = min(desc.alpha * B, n)
+        lines = [_loop_lines(desc.seed, s, 1 if l < desc.L_loc else 2,
+                             l if l < desc.L_loc else l - desc.L_loc, n, w) for l in range(L)]
+        u = np.unique(np.concatenate(lines))
+        main += 128 * u.size + L * B * 8
+        probe = [_loop_lines(desc.seed, s, 0, i, n, min(desc.alpha_probe * Bp, n))
+                 for i, Bp in enumerate(t["probe_B"])]
+        up = np.unique(np.concatenate([u] + probe))
+        step += 128 * up.size + L * B * 8 + sum(Bp * 8 for Bp in t["probe_B"])
+    return main, step
+
+
 def cpu_baseline(desc, xs, budget_s):
     """The FP64 oracle, single-threaded, on the first signals of the batch."""
     import oracle
@@ -198,6 +242,8 @@ def main():
         alg_bytes += L * (wlen * 8 + B * 8)
     hash_s = stage_ms["hash_main"] / 1e3
     achieved = alg_bytes / hash_s / 1e9
+    log("touched lines")
+    touched_main, touched_step = touched_bytes(d, trs)
 
     # plain per-signal form
     plan1 = A.Plan(1, n, "c64", seed=PLAN_SEED, max_batch=1)
@@ -273,7 +319,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(batch),
                      "kernel": "k_hash (main loops)", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": stage_ms["hash_main"]},
+                     "avg_launch_ms": stage_ms["hash_main"],
+                     "touched_bytes_per_launch": touched_main,
+                     "touched_frac": touched_main / hash_s / 1e9 / HBM_PEAK_GBS},
+        "touched_bytes_per_step": touched_step,
+        "touched_frac_of_step": touched_step / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
         "dense_fft_ms_per_transform": ms_dense / batch,
         "atsfft_ms_per_transform": ms_step / batch,

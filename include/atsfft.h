@@ -85,7 +85,16 @@ enum {
  *                1D: 2^6 <= n <= 2^30; 2D: 2^4 <= N <= 2^15.
  *   dtype        ATSFFT_C64 or ATSFFT_C128 (input, values and arithmetic).
  *   max_out      capacity of locs/vals per signal, 1 <= max_out <= 16384.
- *   seed         key of the counter-based SplitMix64 draws of (sigma, tau).
+ *   seed         key of the counter-based SplitMix64 draws of (sigma, tau)
+ *                (Definition 1's random spectral permutation): the loop of
+ *                phase p (0 probe, 1 location, 2 estimation), iteration i
+ *                (probe level, or loop index within its phase) and axis a of
+ *                signal s (its index in the call) takes r = the SplitMix64
+ *                output at index ((s * 4 + p) * 256 + i) * 2 + a, i.e. the
+ *                variant-13 finaliser of seed + (index + 1) * 0x9E3779B97F4A7C15
+ *                (mod 2^64); sigma = (r mod n) | 1, tau = (r >> 32) mod n.
+ *                The loop samples x[(sigma * t + tau) mod n] for the taps
+ *                t in [-w/2, w/2).
  *   B0, B_max    first and largest bucket count per axis (powers of two);
  *                B_max^ndim complex values must fit the device's LDS twice.
  *   alpha_probe, alpha   window length factors (w = alpha * B, capped at n),
