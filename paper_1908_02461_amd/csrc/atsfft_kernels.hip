@@ -196,24 +196,32 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
 
 // The k-th smallest (0-based) of m[0..cnt) in LDS, by most-significant-digit
 // radix selection on the bit patterns (the values are non-negative, so their
-// patterns order like the values).  `hist` has 256 words, `sh` 2.
+// patterns order like the values).  `hist` has 2 x 256 words, used in turn so
+// that each pass clears the next pass's histogram while it counts; `sh` has 4
+// words (the chosen digit and rank, also in turn).
 template <typename R>
 __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
                                                 uint32_t *sh) {
   using K = typename CT<R>::K;
   constexpr int NB = sizeof(K) * 8;
   K prefix = 0, mask = 0;
-  for (int shift = NB - 8; shift >= 0; shift -= 8) {
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  int pass = 0;
+  for (int shift = NB - 8; shift >= 0; shift -= 8, ++pass) {
+    uint32_t *h = hist + 256 * (pass & 1);
+    uint32_t *hn = hist + 256 * ((pass + 1) & 1);
+    uint32_t *out = sh + 2 * (pass & 1);
     for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
       const K key = key_of(m[b]);
-      if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+      if ((key & mask) == prefix) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
     }
+    if (shift > 0)
+      for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hn[i] = 0;
     __syncthreads();
     if (threadIdx.x < 64) {
       const uint32_t l = threadIdx.x;
-      const uint32_t c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+      const uint32_t c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
       const uint32_t s = c0 + c1 + c2 + c3;
       const uint32_t incl = wave_incl_scan(s);
       const uint32_t excl = incl - s;
@@ -232,17 +240,17 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
           digit = 4 * l + 3;
           run = excl + c0 + c1 + c2;
         }
-        sh[0] = digit;
-        sh[1] = k - run;
+        out[0] = digit;
+        out[1] = k - run;
       }
     }
     __syncthreads();
-    const uint32_t digit = sh[0];
-    k = sh[1];
+    const uint32_t digit = out[0];
+    k = out[1];
     prefix |= (K)digit << shift;
     mask |= (K)255u << shift;
-    __syncthreads();
   }
+  __syncthreads();
   return val_of(prefix);
 }
 
@@ -448,43 +456,134 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
 
 // --------------------------------------------------------- LDS FFT ----
 
-// Radix-2 decimation-in-time passes along one axis of `count` independent
-// length-2^logB transforms held in LDS in bit-reversed order; element j of
-// transform f sits at buf[f * fstride + j * estride].  Unnormalised, with
-// omega = e^{-2 pi i / B} (the DFT display).
+// In-register DFTs of 2, 4 and 8 points, natural order in and out,
+// omega = e^{-2 pi i / RAD}.
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C> __device__ __forceinline__ C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C> __device__ __forceinline__ C mul_mi(C a) {  // a * (-i)
+  C r;
+  r.x = a.y;
+  r.y = -a.x;
+  return r;
+}
+
+template <typename C> __device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, C &x3) {
+  const C a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = mul_mi(csub(x1, x3));
+  x0 = cadd(a0, a2);
+  x2 = csub(a0, a2);
+  x1 = cadd(a1, a3);
+  x3 = csub(a1, a3);
+}
+
+template <typename R, int RB> __device__ __forceinline__ void dft_reg(typename CT<R>::C *x) {
+  using C = typename CT<R>::C;
+  if (RB == 1) {
+    const C a = x[0];
+    x[0] = cadd(a, x[1]);
+    x[1] = csub(a, x[1]);
+  } else if (RB == 2) {
+    dft4(x[0], x[1], x[2], x[3]);
+  } else {
+    // split into even and odd halves, then X_m = E_m + w8^m O_m and
+    // X_{m+4} = E_m - w8^m O_m with w8 = e^{-i pi / 4}
+    C e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6], o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const R h = (R)0.70710678118654752440084436210484904;
+    C t1, t3;
+    t1.x = h * (o1.x + o1.y);
+    t1.y = h * (o1.y - o1.x);
+    const C t2 = mul_mi(o2);
+    t3.x = h * (o3.y - o3.x);
+    t3.y = -h * (o3.x + o3.y);
+    x[0] = cadd(e0, o0);
+    x[4] = csub(e0, o0);
+    x[1] = cadd(e1, t1);
+    x[5] = csub(e1, t1);
+    x[2] = cadd(e2, t2);
+    x[6] = csub(e2, t2);
+    x[3] = cadd(e3, t3);
+    x[7] = csub(e3, t3);
+  }
+}
+
+// One pass of the in-place decimation-in-time DFT on bit-reversed input: the
+// completed sub-transforms of length L = 2^logL are combined RAD = 2^RB at a
+// time into length RAD L.  For offset p < L the RAD inputs are taken from
+// sub-transforms in bit-reversed order (which is how the radix-2 stages this
+// pass replaces would have paired them), scaled by omega_{RAD L}^{j p}, and
+// transformed in registers; output m goes to position p + m L.
+template <typename R, int RB>
+__device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, uint32_t logL, uint32_t count,
+                                         uint32_t fstride, uint32_t estride) {
+  using C = typename CT<R>::C;
+  constexpr int RAD = 1 << RB;
+  const uint32_t gl = logB - RB;  // log2 of the groups per transform
+  const uint32_t total = count << gl;
+  const uint32_t L = 1u << logL;
+  const R inv_n2 = (R)1 / (R)(L << RB);
+  for (uint32_t kk = threadIdx.x; kk < total; kk += blockDim.x) {
+    const uint32_t f = kk >> gl, q = kk & ((1u << gl) - 1u);
+    const uint32_t p = q & (L - 1u), g = q >> logL;
+    C *base = buf + f * fstride + (((g << (logL + RB)) + p) * estride);
+    const uint32_t step = L * estride;
+    C x[RAD];
+#pragma unroll
+    for (int j = 0; j < RAD; ++j) {
+      const int jr = RB == 1 ? j : RB == 2 ? ((j & 1) << 1 | (j >> 1)) : ((j & 1) << 2 | (j & 2) | (j >> 2));
+      x[j] = base[(uint32_t)jr * step];
+    }
+    if (logL > 0) {
+      C w1;  // omega_{RAD L}^p, the angle an exact multiple of pi
+      sincos_pi((R)(-2) * (R)p * inv_n2, &w1.y, &w1.x);
+      C wj = w1;
+#pragma unroll
+      for (int j = 1; j < RAD; ++j) {
+        x[j] = cmul(x[j], wj);
+        if (j + 1 < RAD) wj = cmul(wj, w1);
+      }
+    }
+    dft_reg<R, RB>(x);
+#pragma unroll
+    for (int m = 0; m < RAD; ++m) base[(uint32_t)m * step] = x[m];
+  }
+  __syncthreads();
+}
+
+// Unnormalised DFT with omega = e^{-2 pi i / B} (the DFT display) along one
+// axis of `count` independent length-2^logB transforms held in LDS in
+// bit-reversed order; element j of transform f sits at
+// buf[f * fstride + j * estride].  Radix-8 passes, led by one radix-2 or
+// radix-4 pass when log2 B is not a multiple of 3.
 template <typename R>
 __device__ __forceinline__ void fft_axis(typename CT<R>::C *buf, uint32_t logB, uint32_t count, uint32_t fstride,
-                         uint32_t estride) {
-  using C = typename CT<R>::C;
-  const uint32_t halfB = 1u << (logB - 1);
-  const uint32_t total = count * halfB;
-  for (uint32_t s = 1; s <= logB; ++s) {
-    const uint32_t half = 1u << (s - 1);
-    const R inv_len = (R)1 / (R)(1u << s);
-    for (uint32_t kk = threadIdx.x; kk < total; kk += blockDim.x) {
-      const uint32_t f = kk >> (logB - 1);
-      const uint32_t q = kk & (halfB - 1u);
-      const uint32_t pos = q & (half - 1u);
-      const uint32_t i = ((q >> (s - 1)) << s) + pos;
-      const uint32_t j = i + half;
-      R sn, cs;
-      sincos_pi((R)(-2) * (R)pos * inv_len, &sn, &cs);
-      C *pi = &buf[f * fstride + i * estride];
-      C *pj = &buf[f * fstride + j * estride];
-      const C u = *pi, v = *pj;
-      C vw;
-      vw.x = v.x * cs - v.y * sn;
-      vw.y = v.x * sn + v.y * cs;
-      C o1, o2;
-      o1.x = u.x + vw.x;
-      o1.y = u.y + vw.y;
-      o2.x = u.x - vw.x;
-      o2.y = u.y - vw.y;
-      *pi = o1;
-      *pj = o2;
-    }
-    __syncthreads();
+                                         uint32_t estride) {
+  uint32_t logL = 0;
+  const uint32_t lead = logB % 3;
+  if (lead == 1) {
+    fft_pass<R, 1>(buf, logB, 0, count, fstride, estride);
+    logL = 1;
+  } else if (lead == 2) {
+    fft_pass<R, 2>(buf, logB, 0, count, fstride, estride);
+    logL = 2;
   }
+  for (; logL < logB; logL += 3) fft_pass<R, 3>(buf, logB, logL, count, fstride, estride);
 }
 
 // key order of the local-maximum and cutoff steps: larger m first, equal m
@@ -562,63 +661,48 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     fft_axis<R>(buf, logB, B, B, 1);
     fft_axis<R>(buf, logB, B, 1, B);
   }
-  for (uint32_t b = tid; b < Bc; b += T) yg[b] = buf[b];
-  if (main_phase && loop >= P.L_loc) return;
-
-  // m_b = |y_hat_b|^2 in LDS; it overwrites the front of the DFT buffer, so
-  // every thread reads its values before any is written.
+  // y_hat back to the workspace; for probe and location loops also
+  // m_b = |y_hat_b|^2 and the largest key, kept in registers while the DFT
+  // buffer is still being read, then m written over the buffer's front
+  using K = typename CT<R>::K;
   const uint32_t per = (Bc + T - 1) / T;
-  R *ms = reinterpret_cast<R *>(smem);
-  {
-    R mv[kBucketMaxPer];
+  const bool stats = !(main_phase && loop >= P.L_loc);
+  R mv[kBucketMaxPer];
+  K kmax = 0;
 #pragma unroll
-    for (int j = 0; j < kBucketMaxPer; ++j) {
-      const uint32_t b = tid + (uint32_t)j * T;
-      mv[j] = 0;
-      if ((uint32_t)j < per && b < Bc) {
-        const C v = buf[b];
-        mv[j] = v.x * v.x + v.y * v.y;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kBucketMaxPer; ++j) {
-      const uint32_t b = tid + (uint32_t)j * T;
-      if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
+  for (int j = 0; j < kBucketMaxPer; ++j) {
+    const uint32_t b = tid + (uint32_t)j * T;
+    mv[j] = 0;
+    if ((uint32_t)j < per && b < Bc) {
+      const C v = buf[b];
+      yg[b] = v;
+      mv[j] = v.x * v.x + v.y * v.y;
+      kmax = max(kmax, key_of(mv[j]));
     }
   }
+  if (!stats) return;
+  for (int o = 32; o > 0; o >>= 1) {
+    const K other = __shfl_xor(kmax, o);
+    kmax = max(kmax, other);
+  }
+  R *ms = reinterpret_cast<R *>(smem);
   unsigned char *flags = smem + (size_t)Bc * sizeof(R);
   uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + Bc + 15) & ~(size_t)15));
-  uint32_t *sh = hist + 256;  // 32 words of scratch
-  if (tid == 0) {
-    sh[28] = 0;
-    sh[29] = 0;
+  uint32_t *sh = hist + 512;               // 32 words of scratch
+  K *wmax = reinterpret_cast<K *>(sh + 32);  // one key per wave
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kBucketMaxPer; ++j) {
+    const uint32_t b = tid + (uint32_t)j * T;
+    if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
   }
+  if ((tid & 63) == 0) wmax[tid >> 6] = kmax;
   __syncthreads();
 
   // threshold: noise floor from the floor(q (Bc-1))-th order statistic,
   // c_noise = ln(Bc / noise_rate), and the relative floor rho * max m
-  {
-    typename CT<R>::K kmax = 0;
-    for (uint32_t b = tid; b < Bc; b += T) kmax = max(kmax, key_of(ms[b]));
-    for (int o = 32; o > 0; o >>= 1) {
-      typename CT<R>::K other = __shfl_xor(kmax, o);
-      kmax = max(kmax, other);
-    }
-    if ((tid & 63) == 0) {
-      if (sizeof(R) == 4)
-        atomicMax(reinterpret_cast<uint32_t *>(&sh[28]), (uint32_t)kmax);
-      else
-        atomicMax(reinterpret_cast<unsigned long long *>(&sh[28]), (unsigned long long)kmax);
-    }
-  }
-  __syncthreads();
-  R mmax;
-  if (sizeof(R) == 4)
-    mmax = val_of((typename CT<R>::K)sh[28]);
-  else
-    mmax = val_of(*reinterpret_cast<typename CT<R>::K *>(&sh[28]));
-  __syncthreads();
+  for (uint32_t wv = 0; wv < (T + 63) / 64; ++wv) kmax = max(kmax, wmax[wv]);
+  const R mmax = val_of(kmax);
   const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
   const R floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh);
   const double c_noise = log((double)Bc / P.noise_rate);
@@ -707,15 +791,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   for (uint32_t j = 0; j < cnt; ++j)
     if (flags[start + j]) jl[pos++] = (int32_t)(start + j);
   __syncthreads();
+  // the cutoff bitmap, 64 buckets per wave ballot
   uint32_t *jb = jbits_of(P, sig, loop);
-  const uint32_t words = (Bc + 31) >> 5;
-  for (uint32_t wi = tid; wi < words; wi += T) {
-    uint32_t word = 0;
-    for (uint32_t bb = 0; bb < 32; ++bb) {
-      const uint32_t b = (wi << 5) + bb;
-      if (b < Bc && flags[b]) word |= 1u << bb;
+  for (uint32_t b0 = tid & ~63u; b0 < Bc; b0 += T) {
+    const uint32_t b = b0 + (tid & 63u);
+    const unsigned long long bits = __ballot(b < Bc && flags[b]);
+    if ((tid & 63u) == 0) {
+      jb[b0 >> 5] = (uint32_t)bits;
+      if (b0 + 32 < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(bits >> 32);
     }
-    jb[wi] = word;
   }
   if (tid == 0) {
     jcount_of(P, sig)[loop] = (int32_t)total;
@@ -1361,7 +1445,7 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
   const size_t fft = 2 * rs * Bc_max;
-  const size_t sel = ((rs * Bc_max + Bc_max + 15) & ~(size_t)15) + 4 * (256 + 32);
+  const size_t sel = ((rs * Bc_max + Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
 
