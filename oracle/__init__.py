@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 PHASE_PROBE, PHASE_LOC, PHASE_EST = 0, 1, 2
-OK, TRUNCATED, PROBE_NOT_CONVERGED, PROBE_SATURATED, EMPTY = 0, 1, 2, 4, 8
+OK, TRUNCATED, PROBE_NOT_CONVERGED, PROBE_SATURATED, EMPTY, RETRIED = 0, 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:
@@ -70,6 +70,8 @@ class _Params(C.Structure):
         ("fixed_B", C.c_int64),
         ("fixed_k", C.c_int64),
         ("max_out", C.c_int64),
+        ("res_tol", C.c_double),
+        ("res_retries", C.c_int),
     ]
 
 
@@ -96,6 +98,8 @@ class _Result(C.Structure):
         ("locs", C.POINTER(C.c_int64)),
         ("vals", C.POINTER(C.c_double)),
         ("est", C.POINTER(C.c_double)),
+        ("res_ratio", C.c_double),
+        ("retries", C.c_int),
     ]
 
 
@@ -149,6 +153,11 @@ def _declare(L):
     L.or_l1_error.argtypes = [C.c_int64, _D, C.c_int64, _I64, _D, C.c_int64]
     L.or_default_params.restype = None
     L.or_default_params.argtypes = [C.POINTER(_Params), C.c_int, C.c_int64]
+    L.or_residual_reach.restype = C.c_int
+    L.or_residual_reach.argtypes = [C.c_int, C.c_double]
+    L.or_residual.restype = None
+    L.or_residual.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_int64, _D, C.c_int, C.c_int, _I64, _I64, _D,
+                              C.c_int64, _I64, _D, _D, _D]
     L.or_atsfft.restype = C.c_int
     L.or_atsfft.argtypes = [C.POINTER(_Params), _D, C.POINTER(_Result)]
 
@@ -297,6 +306,28 @@ def vote_hist(ndim, n, B, sigma_inv, J):
     return votes
 
 
+def residual_reach(alpha, delta) -> int:
+    return int(lib().or_residual_reach(alpha, delta))
+
+
+def residual(ndim, n, B, w, G, sigma, tau, yhat, locs, vals, reach):
+    """Residual test (an addition to the method): E_res, E_tot of the loops'
+    bucket DFTs yhat [L][B^ndim] against the model of the located values, with
+    per-loop draws sigma, tau [L] (1D) or [L][2] (2D), the model reaching
+    `reach` buckets to each side of a frequency's own."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    s = np.ascontiguousarray(sigma, dtype=np.int64)
+    t = np.ascontiguousarray(tau, dtype=np.int64)
+    y = _c128(yhat)
+    L = y.shape[0]
+    locs = np.ascontiguousarray(locs, dtype=np.int64)
+    vals = _c128(vals)
+    er, et = C.c_double(), C.c_double()
+    lib().or_residual(ndim, n, B, w, _dp(G), reach, L, s.ctypes.data_as(_I64), t.ctypes.data_as(_I64), _dp(y),
+                      locs.size, locs.ctypes.data_as(_I64), _dp(vals), C.byref(er), C.byref(et))
+    return er.value, et.value
+
+
 def median(v) -> float:
     v = np.ascontiguousarray(v, dtype=np.float64)
     return float(lib().or_median(_dp(v), v.size))
@@ -335,6 +366,8 @@ class Params:
     fixed_B: int = 0
     fixed_k: int = 0
     max_out: int = 4096
+    res_tol: float = 0.0
+    res_retries: int = 1
 
     @staticmethod
     def defaults(ndim: int, n: int, **kw) -> "Params":
@@ -357,6 +390,8 @@ def atsfft(x, p: Params, trace: bool = True) -> dict:
     x = _c128(x)
     lib()
     B = p.fixed_B if p.fixed_B > 0 else p.B_max
+    if p.res_tol > 0:
+        B = max(B, p.B_max)
     cnt = B if p.ndim == 1 else B * B
     L = p.L_loc + p.L_est
     r = _Result()
@@ -392,6 +427,8 @@ def atsfft(x, p: Params, trace: bool = True) -> dict:
         "probe_decision": [int(r.probe_decision[i]) for i in range(r.n_probe)],
         "T_loc": [float(r.T_loc[i]) for i in range(p.L_loc)],
         "J_count": [int(r.J_count[i]) for i in range(p.L_loc)],
+        "res_ratio": float(r.res_ratio),
+        "retries": int(r.retries),
     }
     if trace and not (r.status & EMPTY):
         c = int(r.B_star) if p.ndim == 1 else int(r.B_star) ** 2

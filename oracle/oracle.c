@@ -510,6 +510,8 @@ void or_default_params(or_params *p, int ndim, int64_t n) {
   p->fixed_B = 0;
   p->fixed_k = 0;
   p->max_out = 4096;
+  p->res_tol = 0.0;
+  p->res_retries = 1;
 }
 
 static int is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -532,6 +534,232 @@ static void hash_loop(const or_params *p, const double *x, int phase, int iter, 
 
 static int64_t bcount(int ndim, int64_t B) { return ndim == 1 ? B : B * B; }
 
+/* Reach of the residual model in buckets on each side of a frequency's own
+   bucket: the window's response falls to delta by n/(2B) + D, with the
+   transition half-width D = (n/B) 2 ln(1/delta) / (pi alpha) of the Gaussian
+   (the window paragraph of Sec. II-A-2 read as Gaussian times Dirichlet), and
+   bucket h + j covers offsets up to (j + 1/2) n/B, so R = ceil(D B / n)
+   buckets reach every response above delta. */
+int or_residual_reach(int alpha, double delta) {
+  double d = 2.0 * log(1.0 / delta) / (OR_PI * (double)alpha);
+  int R = (int)ceil(d);
+  return R < 1 ? 1 : R;
+}
+
+/* Residual energy of the estimation loops against the bucket values the
+   located set predicts (a check added to the method, not in the paper).  By
+   Lemma 1 and the fold, a coefficient X_f puts X_f omega^{-tau f} G'(q) into
+   bucket b with q = b n/B - sigma f (per axis, centred mod n); the model keeps
+   every located f in the buckets h - R .. h + R around its own bucket h (per
+   axis; R at most (B-1)/2 so no bucket is reached twice).  E_res = sum over
+   loops and buckets of |yhat - model|^2, E_tot = sum of |yhat|^2. */
+void or_residual(int ndim, int64_t n, int64_t B, int64_t w, const double *G, int R, int L,
+                 const int64_t *sigma, const int64_t *tau, const double *yhat, int64_t S, const int64_t *locs,
+                 const double *vals, double *E_res, double *E_tot) {
+  int64_t cnt = ndim == 1 ? B : B * B;
+  int64_t nb = n / B;
+  if (R > (B - 1) / 2) R = (int)((B - 1) / 2);
+  int span = 2 * R + 1;
+  int64_t half = (int64_t)(R + 1) * nb; /* |q| <= (R + 1/2) n/B */
+  double *M = (double *)malloc(sizeof(double) * 2 * (size_t)cnt);
+  double *gq = (double *)malloc(sizeof(double) * (size_t)(2 * half + 1));
+  uint8_t *gq_done = (uint8_t *)calloc((size_t)(2 * half + 1), 1);
+  int64_t *hb = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)span);
+  double *gb = (double *)malloc(sizeof(double) * 2 * (size_t)span);
+  double er = 0.0, et = 0.0;
+  for (int l = 0; l < L; l++) {
+    const double *y = yhat + 2 * (size_t)l * (size_t)cnt;
+    for (int64_t b = 0; b < 2 * cnt; b++) M[b] = 0.0;
+    for (int64_t s = 0; s < S; s++) {
+      int64_t f = locs[s];
+      int64_t fa[2] = {ndim == 1 ? f : f / n, ndim == 1 ? 0 : f % n};
+      int64_t ph = 0;
+      /* per axis: buckets h + j, j in [-R, R], with q = o + j n/B */
+      for (int a = 0; a < ndim; a++) {
+        int64_t h = or_hash_bucket(n, B, sigma[ndim * l + a], fa[a]);
+        int64_t o = or_hash_offset(n, B, sigma[ndim * l + a], fa[a]);
+        for (int j = -R; j <= R; j++) {
+          int64_t q = o + (int64_t)j * nb;
+          if (!gq_done[q + half]) {
+            gq[q + half] = or_window_hat(n, w, G, q, NULL);
+            gq_done[q + half] = 1;
+          }
+          hb[a * span + (j + R)] = ((h + j) % B + B) % B;
+          gb[a * span + (j + R)] = gq[q + half];
+        }
+        ph = (ph + (tau[ndim * l + a] % n) * fa[a]) % n;
+      }
+      /* X_f omega^{-tau f} */
+      double wr, wi;
+      omega_pow(n, (n - ph) % n, &wr, &wi);
+      double cr = vals[2 * s] * wr - vals[2 * s + 1] * wi;
+      double ci = vals[2 * s] * wi + vals[2 * s + 1] * wr;
+      int s2 = ndim == 1 ? 1 : span;
+      for (int i = 0; i < span; i++)
+        for (int j = 0; j < s2; j++) {
+          double g = gb[i] * (ndim == 1 ? 1.0 : gb[span + j]);
+          int64_t b = ndim == 1 ? hb[i] : hb[i] * B + hb[span + j];
+          M[2 * b] += cr * g;
+          M[2 * b + 1] += ci * g;
+        }
+    }
+    for (int64_t b = 0; b < cnt; b++) {
+      double dr = y[2 * b] - M[2 * b], di = y[2 * b + 1] - M[2 * b + 1];
+      er += dr * dr + di * di;
+      et += y[2 * b] * y[2 * b] + y[2 * b + 1] * y[2 * b + 1];
+    }
+  }
+  *E_res = er;
+  *E_tot = et;
+  free(M);
+  free(gq);
+  free(gq_done);
+  free(hb);
+  free(gb);
+}
+
+/* Location loops, vote and estimation at bucket count B_star (per axis) with
+   the draws of pass `pass` (iteration index offset by 32 per pass); fills the
+   located set, values and trace of r.  With the residual test enabled,
+   *ratio = E_res / E_tot of the estimation loops. */
+static void main_phase(const or_params *p, const double *x, int64_t B_star, int64_t khat, int pass,
+                       or_result *r, double *ratio) {
+  int64_t n = p->n;
+  int nd = p->ndim;
+  int off = 32 * pass;
+  int64_t cnt = bcount(nd, B_star);
+  double *yh = (double *)malloc(sizeof(double) * 2 * (size_t)cnt);
+  double *m = (double *)malloc(sizeof(double) * (size_t)cnt);
+  int64_t sig[2], tau[2], sinv[2];
+  int keep_trace = cnt <= r->yhat_stride;
+  r->status &= ~OR_TRUNCATED;
+
+  /* ---- location loops: hash, DFT, cutoff, reverse hash (votes) ---- */
+  int64_t num = (int64_t)p->d * khat;
+  if (num > cnt) num = cnt;
+  uint8_t *J = (uint8_t *)calloc((size_t)(p->L_loc * cnt), 1);
+  int64_t *sinv_loc = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)p->L_loc);
+  for (int l = 0; l < p->L_loc; l++) {
+    hash_loop(p, x, OR_PHASE_LOC, off + l, B_star, p->alpha, yh, sig, tau, sinv);
+    for (int64_t b = 0; b < cnt; b++) m[b] = yh[2 * b] * yh[2 * b] + yh[2 * b + 1] * yh[2 * b + 1];
+    double T = or_threshold(m, cnt, p->q, p->noise_rate, p->rho);
+    r->T_loc[l] = T;
+    r->J_count[l] = or_topnum(m, cnt, T, num, J + (size_t)l * (size_t)cnt);
+    for (int a = 0; a < nd; a++) sinv_loc[nd * l + a] = sinv[a];
+    if (r->yhat && keep_trace)
+      memcpy(r->yhat + 2 * (size_t)l * (size_t)r->yhat_stride, yh, sizeof(double) * 2 * (size_t)cnt);
+    if (r->J && keep_trace)
+      memcpy(r->J + (size_t)l * (size_t)r->yhat_stride, J + (size_t)l * (size_t)cnt, (size_t)cnt);
+  }
+  int64_t total = nd == 1 ? n : n * n;
+  int32_t *votes = (int32_t *)calloc((size_t)total, sizeof(int32_t));
+  or_vote_hist(nd, n, B_star, p->L_loc, sinv_loc, J, votes);
+  int64_t S = 0;
+  for (int64_t f = 0; f < total; f++)
+    if (votes[f] >= p->T_vote) S++;
+  r->count = S;
+  if (S > p->max_out) r->status |= OR_TRUNCATED;
+
+  /* ---- estimation loops: hash, estimate, median ---- */
+  int64_t *Sl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
+  int64_t si = 0;
+  for (int64_t f = 0; f < total; f++)
+    if (votes[f] >= p->T_vote) Sl[si++] = f;
+  double *e = (double *)malloc(sizeof(double) * 2 * (size_t)(S > 0 ? S : 1) * (size_t)p->L_est);
+  int64_t w = or_window_len(n, B_star, p->alpha);
+  double *G = (double *)malloc(sizeof(double) * (size_t)w);
+  or_window_taps(n, B_star, w, p->delta, G);
+  /* the estimation loops' bucket DFTs and draws, kept for the residual */
+  int want_res = p->res_tol > 0.0;
+  double *yest = want_res ? (double *)malloc(sizeof(double) * 2 * (size_t)cnt * (size_t)p->L_est) : NULL;
+  int64_t *sig_est = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)p->L_est);
+  int64_t *tau_est = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)p->L_est);
+  /* G'(o) for o in (-n/(2B), n/(2B)], each evaluated once, on first use */
+  int64_t cB = n / (2 * B_star);
+  double *ghat = (double *)malloc(sizeof(double) * (size_t)(2 * cB + 1));
+  uint8_t *ghat_done = (uint8_t *)calloc((size_t)(2 * cB + 1), 1);
+  for (int l = 0; l < p->L_est; l++) {
+    hash_loop(p, x, OR_PHASE_EST, off + l, B_star, p->alpha, yh, sig, tau, sinv);
+    for (int a = 0; a < nd; a++) {
+      sig_est[nd * l + a] = sig[a];
+      tau_est[nd * l + a] = tau[a];
+    }
+    if (yest) memcpy(yest + 2 * (size_t)l * (size_t)cnt, yh, sizeof(double) * 2 * (size_t)cnt);
+    if (r->yhat && keep_trace)
+      memcpy(r->yhat + 2 * (size_t)(p->L_loc + l) * (size_t)r->yhat_stride, yh,
+             sizeof(double) * 2 * (size_t)cnt);
+    for (int64_t s = 0; s < S; s++) {
+      int64_t f = Sl[s];
+      int64_t fa[2] = {nd == 1 ? f : f / n, nd == 1 ? 0 : f % n};
+      int64_t hb = 0, phase = 0;
+      double gh = 1.0;
+      for (int a = 0; a < nd; a++) {
+        int64_t h = or_hash_bucket(n, B_star, sig[a], fa[a]);
+        int64_t o = or_hash_offset(n, B_star, sig[a], fa[a]);
+        hb = hb * B_star + h;
+        phase = (phase + (tau[a] * fa[a]) % n) % n;
+        if (!ghat_done[o + cB]) {
+          ghat[o + cB] = or_window_hat(n, w, G, o, NULL);
+          ghat_done[o + cB] = 1;
+        }
+        gh *= ghat[o + cB];
+      }
+      /* the estimator display: yhat_h omega^{tau f} / G'(o) */
+      double wr, wi;
+      omega_pow(n, phase, &wr, &wi);
+      double zr = yh[2 * hb] * wr - yh[2 * hb + 1] * wi;
+      double zi = yh[2 * hb] * wi + yh[2 * hb + 1] * wr;
+      e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l)] = zr / gh;
+      e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l) + 1] = zi / gh;
+    }
+  }
+  /* a truncated pass has no values to model: it counts as an infinite ratio */
+  *ratio = want_res && (r->status & OR_TRUNCATED) ? HUGE_VAL : 0.0;
+  if (!(r->status & OR_TRUNCATED)) {
+    double *re = (double *)malloc(sizeof(double) * (size_t)p->L_est);
+    double *im = (double *)malloc(sizeof(double) * (size_t)p->L_est);
+    double *V = (double *)malloc(sizeof(double) * 2 * (size_t)(S > 0 ? S : 1));
+    for (int64_t s = 0; s < S; s++) {
+      for (int l = 0; l < p->L_est; l++) {
+        re[l] = e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l)];
+        im[l] = e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l) + 1];
+      }
+      V[2 * s] = or_median(re, p->L_est);
+      V[2 * s + 1] = or_median(im, p->L_est);
+      if (r->locs) r->locs[s] = Sl[s];
+      if (r->vals) {
+        r->vals[2 * s] = V[2 * s];
+        r->vals[2 * s + 1] = V[2 * s + 1];
+      }
+      if (r->est)
+        memcpy(r->est + 2 * (size_t)s * (size_t)p->L_est, e + 2 * (size_t)s * (size_t)p->L_est,
+               sizeof(double) * 2 * (size_t)p->L_est);
+    }
+    if (want_res) {
+      double er, et;
+      or_residual(nd, n, B_star, w, G, or_residual_reach(p->alpha, p->delta), p->L_est, sig_est, tau_est,
+                  yest, S, Sl, V, &er, &et);
+      *ratio = et > 0.0 ? er / et : 0.0;
+    }
+    free(V);
+    free(re);
+    free(im);
+  }
+  free(yest);
+  free(sig_est);
+  free(tau_est);
+  free(ghat);
+  free(ghat_done);
+  free(G);
+  free(e);
+  free(Sl);
+  free(votes);
+  free(sinv_loc);
+  free(J);
+  free(yh);
+  free(m);
+}
+
 int or_atsfft(const or_params *p, const double *x, or_result *r) {
   int64_t n = p->n;
   int nd = p->ndim;
@@ -540,12 +768,15 @@ int or_atsfft(const or_params *p, const double *x, or_result *r) {
       p->L_est < 1 || p->L_est > OR_TRACE_MAX_LOOPS || (p->L_est % 2) == 0 || p->T_vote < 1 ||
       p->T_vote > p->L_loc || p->P_max < 1 || p->P_max > OR_TRACE_MAX_PROBE || p->d < 1 ||
       !(p->delta > 0.0 && p->delta < 1.0) || !(p->q > 0.0 && p->q < 1.0) ||
-      (p->fixed_B > 0 && (!is_pow2(p->fixed_B) || p->fixed_B > n)))
+      (p->fixed_B > 0 && (!is_pow2(p->fixed_B) || p->fixed_B > n)) || p->res_tol < 0.0 ||
+      p->res_retries < 0 || p->res_retries > 7)
     return -1;
 
   r->status = OR_OK;
   r->count = 0;
   r->n_probe = 0;
+  r->res_ratio = 0.0;
+  r->retries = 0;
   int64_t Bcap = p->fixed_B > 0 ? p->fixed_B : p->B_max;
   double *yh = (double *)malloc(sizeof(double) * 2 * (size_t)bcount(nd, Bcap));
   double *m = (double *)malloc(sizeof(double) * (size_t)bcount(nd, Bcap));
@@ -620,103 +851,23 @@ int or_atsfft(const or_params *p, const double *x, or_result *r) {
     return 0;
   }
 
-  /* ---- location loops: hash, DFT, cutoff, reverse hash (votes) ---- */
-  int64_t cnt = bcount(nd, B_star);
-  int64_t num = (int64_t)p->d * khat;
-  if (num > cnt) num = cnt;
-  uint8_t *J = (uint8_t *)calloc((size_t)(p->L_loc * cnt), 1);
-  int64_t *sinv_loc = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)p->L_loc);
-  for (int l = 0; l < p->L_loc; l++) {
-    hash_loop(p, x, OR_PHASE_LOC, l, B_star, p->alpha, yh, sig, tau, sinv);
-    for (int64_t b = 0; b < cnt; b++) m[b] = yh[2 * b] * yh[2 * b] + yh[2 * b + 1] * yh[2 * b + 1];
-    double T = or_threshold(m, cnt, p->q, p->noise_rate, p->rho);
-    r->T_loc[l] = T;
-    r->J_count[l] = or_topnum(m, cnt, T, num, J + (size_t)l * (size_t)cnt);
-    for (int a = 0; a < nd; a++) sinv_loc[nd * l + a] = sinv[a];
-    if (r->yhat) memcpy(r->yhat + 2 * (size_t)l * (size_t)r->yhat_stride, yh, sizeof(double) * 2 * (size_t)cnt);
-    if (r->J) memcpy(r->J + (size_t)l * (size_t)r->yhat_stride, J + (size_t)l * (size_t)cnt, (size_t)cnt);
-  }
-  int64_t total = nd == 1 ? n : n * n;
-  int32_t *votes = (int32_t *)calloc((size_t)total, sizeof(int32_t));
-  or_vote_hist(nd, n, B_star, p->L_loc, sinv_loc, J, votes);
-  int64_t S = 0;
-  for (int64_t f = 0; f < total; f++)
-    if (votes[f] >= p->T_vote) S++;
-  r->count = S;
-  if (S > p->max_out) r->status |= OR_TRUNCATED;
-
-  /* ---- estimation loops: hash, estimate, median ---- */
-  int64_t *Sl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
-  int64_t si = 0;
-  for (int64_t f = 0; f < total; f++)
-    if (votes[f] >= p->T_vote) Sl[si++] = f;
-  double *e = (double *)malloc(sizeof(double) * 2 * (size_t)(S > 0 ? S : 1) * (size_t)p->L_est);
-  int64_t w = or_window_len(n, B_star, p->alpha);
-  double *G = (double *)malloc(sizeof(double) * (size_t)w);
-  or_window_taps(n, B_star, w, p->delta, G);
-  /* G'(o) for o in (-n/(2B), n/(2B)], each evaluated once, on first use */
-  int64_t cB = n / (2 * B_star);
-  double *ghat = (double *)malloc(sizeof(double) * (size_t)(2 * cB + 1));
-  uint8_t *ghat_done = (uint8_t *)calloc((size_t)(2 * cB + 1), 1);
-  for (int l = 0; l < p->L_est; l++) {
-    hash_loop(p, x, OR_PHASE_EST, l, B_star, p->alpha, yh, sig, tau, sinv);
-    if (r->yhat)
-      memcpy(r->yhat + 2 * (size_t)(p->L_loc + l) * (size_t)r->yhat_stride, yh,
-             sizeof(double) * 2 * (size_t)cnt);
-    for (int64_t s = 0; s < S; s++) {
-      int64_t f = Sl[s];
-      int64_t fa[2] = {nd == 1 ? f : f / n, nd == 1 ? 0 : f % n};
-      int64_t hb = 0, phase = 0;
-      double gh = 1.0;
-      for (int a = 0; a < nd; a++) {
-        int64_t h = or_hash_bucket(n, B_star, sig[a], fa[a]);
-        int64_t o = or_hash_offset(n, B_star, sig[a], fa[a]);
-        hb = hb * B_star + h;
-        phase = (phase + (tau[a] * fa[a]) % n) % n;
-        if (!ghat_done[o + cB]) {
-          ghat[o + cB] = or_window_hat(n, w, G, o, NULL);
-          ghat_done[o + cB] = 1;
-        }
-        gh *= ghat[o + cB];
-      }
-      /* the estimator display: yhat_h omega^{tau f} / G'(o) */
-      double wr, wi;
-      omega_pow(n, phase, &wr, &wi);
-      double zr = yh[2 * hb] * wr - yh[2 * hb + 1] * wi;
-      double zi = yh[2 * hb] * wi + yh[2 * hb + 1] * wr;
-      e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l)] = zr / gh;
-      e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l) + 1] = zi / gh;
-    }
-  }
-  if (!(r->status & OR_TRUNCATED)) {
-    double *re = (double *)malloc(sizeof(double) * (size_t)p->L_est);
-    double *im = (double *)malloc(sizeof(double) * (size_t)p->L_est);
-    for (int64_t s = 0; s < S; s++) {
-      for (int l = 0; l < p->L_est; l++) {
-        re[l] = e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l)];
-        im[l] = e[2 * ((size_t)s * (size_t)p->L_est + (size_t)l) + 1];
-      }
-      if (r->locs) r->locs[s] = Sl[s];
-      if (r->vals) {
-        r->vals[2 * s] = or_median(re, p->L_est);
-        r->vals[2 * s + 1] = or_median(im, p->L_est);
-      }
-      if (r->est)
-        memcpy(r->est + 2 * (size_t)s * (size_t)p->L_est, e + 2 * (size_t)s * (size_t)p->L_est,
-               sizeof(double) * 2 * (size_t)p->L_est);
-    }
-    free(re);
-    free(im);
-  }
-  free(ghat);
-  free(ghat_done);
-  free(G);
-  free(e);
-  free(Sl);
-  free(votes);
-  free(sinv_loc);
-  free(J);
+  /* ---- location, vote and estimation at B_star; with the residual test
+     enabled, again at 2 B_star (fresh draws) while the residual is large ---- */
   free(yh);
   free(m);
+  for (int pass = 0;; pass++) {
+    double ratio = 0.0;
+    main_phase(p, x, B_star, khat, pass, r, &ratio);
+    r->res_ratio = ratio;
+    r->retries = pass;
+    int64_t Bcap = p->B_max;
+    if (!(p->res_tol > 0.0) || !(ratio > p->res_tol) || pass >= p->res_retries || 2 * B_star > Bcap ||
+        2 * B_star > n / 2)
+      break;
+    B_star *= 2;
+    r->B_star = B_star;
+    r->status |= OR_RETRIED;
+  }
   return 0;
 }
+

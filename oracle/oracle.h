@@ -31,7 +31,8 @@ enum {
   OR_TRUNCATED = 1,
   OR_PROBE_NOT_CONVERGED = 2,
   OR_PROBE_SATURATED = 4,
-  OR_EMPTY = 8
+  OR_EMPTY = 8,
+  OR_RETRIED = 16 /* the residual test re-ran location and estimation at a larger B */
 };
 
 typedef struct {
@@ -55,6 +56,9 @@ typedef struct {
   int64_t fixed_B;   /* > 0: skip the probe (Algorithm 1 form) */
   int64_t fixed_k;   /* khat used when fixed_B > 0 */
   int64_t max_out;   /* capacity of locs / vals */
+  double res_tol;    /* residual test (an addition to the method): > 0 re-runs location and
+                        estimation at 2 B_star while E_res / E_tot exceeds it; 0 disables */
+  int res_retries;   /* at most this many re-runs (<= 7) */
 } or_params;
 
 #define OR_TRACE_MAX_PROBE 64
@@ -80,9 +84,16 @@ typedef struct {
   int64_t *locs;  /* [max_out] ascending */
   double *vals;   /* [max_out] complex */
   double *est;    /* [max_out][L_est] complex, per-loop estimates */
+  /* residual test */
+  double res_ratio; /* E_res / E_tot of the last pass (0 when the test is off) */
+  int retries;      /* passes re-run at a larger B */
 } or_result;
 
 /* ---- building blocks, each exported so tests can pin it on its own ---- */
+int or_residual_reach(int alpha, double delta);
+void or_residual(int ndim, int64_t n, int64_t B, int64_t w, const double *G, int R, int L,
+                 const int64_t *sigma, const int64_t *tau, const double *yhat, int64_t S, const int64_t *locs,
+                 const double *vals, double *E_res, double *E_tot);
 uint64_t or_splitmix64_at(uint64_t seed, uint64_t index);
 uint64_t or_draw_word(uint64_t seed, uint32_t signal, int phase, int iter, int axis);
 void or_draw(uint64_t seed, uint32_t signal, int phase, int iter, int axis, int64_t n,
