@@ -58,7 +58,8 @@ enum {
   ATSFFT_SIG_TRUNCATED = 1,           /* |S| > max_out: count holds |S|, locs/vals unwritten */
   ATSFFT_SIG_PROBE_NOT_CONVERGED = 2, /* the probe hit its iteration limit */
   ATSFFT_SIG_PROBE_SATURATED = 4,     /* the probe wanted a bucket count above B_max */
-  ATSFFT_SIG_EMPTY = 8                /* the probed sparsity is 0: nothing located */
+  ATSFFT_SIG_EMPTY = 8,               /* the probed sparsity is 0: nothing located */
+  ATSFFT_SIG_RETRIED = 16             /* the residual test re-ran location at a larger B */
 };
 
 /* Descriptor flags. */
@@ -115,6 +116,20 @@ enum {
  *   n_min        0, or the shortest length (power of two) atsfft_execute_uneven
  *                accepts; the plan then also holds tables for every power of
  *                two in [n_min, n), with B0 and B_max clipped to each length.
+ *   res_tol, res_retries   residual test (an addition to the method; the
+ *                paper has none).  res_tol = 0 (the default) disables it.
+ *                Otherwise, after estimation, each estimation loop's bucket
+ *                DFT y_hat is compared with the buckets the located values
+ *                predict by Lemma 1 and the fold (each located f adds
+ *                X_f omega^{-tau f} G'(q), q = b n/B - sigma f, to its own
+ *                bucket and the R = ceil(2 ln(1/delta) / (pi alpha)) buckets
+ *                to each side, R <= (B-1)/2); when E_res / E_tot, summed in
+ *                FP64 over loops and buckets, exceeds res_tol (a truncated
+ *                pass counts as infinite), location and estimation re-run at
+ *                2 B_star with fresh draws (iterations offset by 32 per pass),
+ *                at most res_retries times (<= 7), while 2 B_star <= B_max.
+ *                Re-run signals carry ATSFFT_SIG_RETRIED.  With FIXED_B the
+ *                re-runs may grow past fixed_B up to B_max.
  */
 typedef struct atsfft_desc {
   int32_t ndim;
@@ -141,6 +156,9 @@ typedef struct atsfft_desc {
   int64_t fixed_B;
   int64_t fixed_k;
   int64_t n_min;
+  double res_tol;
+  int32_t res_retries;
+  int32_t pad0;
 } atsfft_desc;
 
 typedef struct atsfft_plan_s *atsfft_plan_t;
@@ -220,9 +238,11 @@ atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *loc
  *   ws_dev         the execute's workspace, unchanged since.
  * Output grad_x_dev, complex, the layout of x: dL/dRe x + i dL/dIm x, written
  * in full (zero where no estimation loop samples).  Signals that were EMPTY
- * or TRUNCATED get a zero gradient.  Contributions of different loops to one
- * address are added with atomics, so the last bits may vary between calls.
- * Errors: ATSFFT_EINVAL, ATSFFT_ELAUNCH.
+ * or TRUNCATED get a zero gradient; after a residual-test re-run the
+ * gradient is that of the last pass.  Every address of grad_x is written
+ * once, its loops added in order; located frequencies that share a bucket add
+ * their bucket cotangents with atomics, so the last bits may vary between
+ * calls.  Errors: ATSFFT_EINVAL, ATSFFT_ELAUNCH.
  */
 atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *grad_vals_dev,
                               const void *ws_dev, void *grad_x_dev, hipStream_t stream);
@@ -245,6 +265,9 @@ typedef struct atsfft_trace {
   int32_t *J_count;
   void *yhat;
   uint32_t *J_bits;
+  double res_ratio; /* residual test: E_res / E_tot of the last pass (0 when off) */
+  int32_t retries;  /* passes re-run at a larger B */
+  int32_t pad0;
 } atsfft_trace;
 
 atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t signal,

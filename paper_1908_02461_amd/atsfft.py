@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libatsfft.so")
 
 SUCCESS, EINVAL, ENODEVICE, ENOMEM, ELAUNCH, ENOTSUPPORTED = range(6)
 C64, C128 = 0, 1
-SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY = 0, 1, 2, 4, 8
+SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY, SIG_RETRIED = 0, 1, 2, 4, 8, 16
 FLAG_FIXED_B = 1
 FLAG_PROFILE = 2
 STAGES = ("probe", "hash_main", "bucket_main", "vote", "estimate")
@@ -50,6 +50,9 @@ class Desc(C.Structure):
         ("fixed_B", C.c_int64),
         ("fixed_k", C.c_int64),
         ("n_min", C.c_int64),
+        ("res_tol", C.c_double),
+        ("res_retries", C.c_int32),
+        ("pad0", C.c_int32),
     ]
 
 
@@ -68,6 +71,9 @@ class Trace(C.Structure):
         ("J_count", C.POINTER(C.c_int32)),
         ("yhat", C.c_void_p),
         ("J_bits", C.POINTER(C.c_uint32)),
+        ("res_ratio", C.c_double),
+        ("retries", C.c_int32),
+        ("pad0", C.c_int32),
     ]
 
 
@@ -169,6 +175,16 @@ class Plan:
     def max_out(self) -> int:
         return int(self.desc.max_out)
 
+    @property
+    def main_bmax(self) -> int:
+        """Largest bucket count per axis of the location and estimation loops
+        (B_max; fixed_B in the Algorithm 1 form, up to B_max with the residual
+        test on)."""
+        d = self.desc
+        if not d.flags & FLAG_FIXED_B:
+            return int(d.B_max)
+        return int(max(d.fixed_B, d.B_max) if d.res_tol > 0 else d.fixed_B)
+
     def workspace_size(self, batch: int) -> int:
         b = C.c_size_t()
         _check(load().atsfft_workspace_size(self._h, batch, C.byref(b)), "atsfft_workspace_size")
@@ -264,7 +280,7 @@ class Plan:
         import torch
 
         d = self.desc
-        Bbig = d.fixed_B if d.flags & FLAG_FIXED_B else d.B_max
+        Bbig = self.main_bmax
         bc = Bbig if self.ndim == 1 else Bbig * Bbig
         L = d.L_loc + d.L_est
         pB = np.zeros(32, np.int32)
@@ -300,6 +316,7 @@ class Plan:
             probe_B=pB[:npb].tolist(), probe_k=pk[:npb].tolist(), probe_decision=pd[:npb].tolist(),
             probe_T=pT[:npb].tolist(), T_loc=tl[: d.L_loc].tolist(), J_count=jc[: d.L_loc].tolist(),
             yhat=yh[:, :c].astype(np.complex128), J=bits[:, :c].astype(bool),
+            res_ratio=float(t.res_ratio), retries=int(t.retries),
         )
 
     def profile_read(self) -> dict:

@@ -24,7 +24,7 @@ struct atsfft_plan_s {
   uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
-  int64_t *tab_dev;  // [96] element offsets by log2 B
+  int64_t *tab_dev;  // [128] element offsets by log2 B
   size_t bucket_smem, est_smem, bwd_smem;
   uint32_t tile_slots;  // hash workgroups per slab and loop
   uint32_t hash_loops;  // main-pass loops per hash workgroup
@@ -84,6 +84,23 @@ void window_taps(int64_t n, int64_t B, int64_t w, double delta, std::vector<doub
   }
 }
 
+// Largest bucket count per axis of the location and estimation loops: B_max,
+// or fixed_B in the Algorithm 1 form (which residual-test re-runs may grow up
+// to B_max).
+int64_t main_bmax(const atsfft_desc *d) {
+  if (!(d->flags & ATSFFT_FLAG_FIXED_B)) return d->B_max;
+  return d->res_tol > 0.0 ? std::max(d->fixed_B, d->B_max) : d->fixed_B;
+}
+
+// Model reach of the residual test in buckets to each side of a frequency's
+// own: ceil(2 ln(1/delta) / (pi alpha)), the Gaussian's transition half-width
+// in bucket widths, at least 1.
+uint32_t residual_reach(const atsfft_desc *d) {
+  const double r = 2.0 * std::log(1.0 / d->delta) / (M_PI * (double)d->alpha);
+  const int v = (int)std::ceil(r);
+  return v < 1 ? 1u : (uint32_t)v;
+}
+
 atsfft_status validate(const atsfft_desc *d) {
   if (!d) return fail(ATSFFT_EINVAL, "null descriptor");
   if (d->ndim != 1 && d->ndim != 2) return fail(ATSFFT_EINVAL, "ndim must be 1 or 2");
@@ -111,7 +128,11 @@ atsfft_status validate(const atsfft_desc *d) {
     if (d->P_max < 1 || d->P_max > kMaxProbe) return fail(ATSFFT_EINVAL, "P_max must be in [1, 32]");
     if (d->gamma < 0) return fail(ATSFFT_EINVAL, "gamma must be >= 0");
   }
-  const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
+  if (!(d->res_tol >= 0.0) || d->res_retries < 0 || d->res_retries > 7)
+    return fail(ATSFFT_EINVAL, "res_tol must be >= 0 and res_retries in [0, 7]");
+  if (fixed && d->res_tol > 0.0 && (!is_pow2(d->B_max) || d->B_max < Bmin || d->B_max > d->n / 2))
+    return fail(ATSFFT_EINVAL, "the residual test needs B_max a power of two in [2, n/2] (2D: [4, N/2])");
+  const int64_t Bbig = main_bmax(d);
   const int64_t Bc = d->ndim == 1 ? Bbig : Bbig * Bbig;
   if (Bc > (int64_t)kBucketThreads * kBucketMaxPer)
     return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384");
@@ -183,6 +204,8 @@ Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
   off = align_up(off + (size_t)d.max_out * 2, A);
   l.bflag = off;
   off = align_up(off + (size_t)kMaxLoops * 4, A);
+  l.resid = off;  // residual test: E_res and E_tot of each estimation loop
+  off = align_up(off + (size_t)2 * kMaxLoops * 8, A);
   l.slice = off;
   l.total = off * (size_t)batch;
   return l;
@@ -240,6 +263,10 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.probe_levels = probe_levels(plan);
   for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
     P.probe_off[i] = i < P.probe_levels ? (uint64_t)kSlabs * probe_offset(plan, i) : 0;
+  P.res_tol = d.res_tol;
+  P.res_retries = (uint32_t)d.res_retries;
+  P.res_reach = residual_reach(&d);
+  P.pass = 0;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;
@@ -316,6 +343,8 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
   d->rho = 1e-6;
   d->fixed_B = 0;
   d->fixed_k = 0;
+  d->res_tol = 0.0;
+  d->res_retries = 1;
   return ATSFFT_SUCCESS;
 }
 
@@ -350,7 +379,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   const bool fixed = (d->flags & ATSFFT_FLAG_FIXED_B) != 0;
   const int64_t n = d->n;
   p->logn = ilog2_host((uint64_t)n);
-  const int64_t Bbig = fixed ? d->fixed_B : d->B_max;
+  const int64_t Bbig = main_bmax(d);
   p->Bc_max = (uint32_t)(d->ndim == 1 ? Bbig : Bbig * Bbig);
   p->bucket_smem = bucket_smem_bytes(d->dtype, p->Bc_max);
   p->hash_loops = 1;
@@ -385,10 +414,12 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
 
   // window tables for every bucket count a loop may use
   std::vector<double> taps_all, ghat_all;
-  std::vector<int64_t> tab(96, 0);
+  std::vector<int64_t> tab(128, 0);
   std::vector<double> taps;
   const int64_t Blo = fixed ? d->fixed_B : d->B0;
-  const int64_t Bhi = fixed ? d->fixed_B : d->B_max;
+  const int64_t Bhi = Bbig;
+  const bool resid = d->res_tol > 0.0;
+  const int64_t reach = (int64_t)residual_reach(d);
   std::vector<int64_t> main_taps_off;
   double *taps_dev64 = nullptr, *ghat_dev64 = nullptr;
   for (int64_t B = Blo; B <= Bhi; B *= 2) {
@@ -405,6 +436,10 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     taps_all.insert(taps_all.end(), taps.begin(), taps.end());
     tab[64 + lb] = (int64_t)ghat_all.size();
     ghat_all.resize(ghat_all.size() + (size_t)(n / B + 1), 0.0);
+    if (resid) {  // G'(q), |q| <= (reach + 1) n/B, for the residual model
+      tab[96 + lb] = (int64_t)ghat_all.size();
+      ghat_all.resize(ghat_all.size() + (size_t)(2 * (reach + 1) * (n / B) + 1), 0.0);
+    }
   }
   // G'(o) from the FP64 taps, on the device
   if (hipMalloc(&taps_dev64, taps_all.size() * sizeof(double)) != hipSuccess ||
@@ -421,6 +456,9 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const int64_t w = std::min<int64_t>((int64_t)d->alpha * B, n);
     ok = launch_window_hat(taps_dev64 + tab[32 + lb], w, n, n / (2 * B), ghat_dev64 + tab[64 + lb], nullptr) ==
          hipSuccess;
+    if (ok && resid)
+      ok = launch_window_hat(taps_dev64 + tab[32 + lb], w, n, (reach + 1) * (n / B), ghat_dev64 + tab[96 + lb],
+                             nullptr) == hipSuccess;
   }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   ok = ok && hipMemcpy(ghat_all.data(), ghat_dev64, ghat_all.size() * sizeof(double), hipMemcpyDeviceToHost) ==
@@ -435,7 +473,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   const size_t rs = d->dtype == ATSFFT_C64 ? sizeof(float) : sizeof(double);
   if (hipMalloc(&p->G_dev, taps_all.size() * rs) != hipSuccess ||
       hipMalloc(&p->Ghat_dev, ghat_all.size() * rs) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&p->tab_dev), 96 * sizeof(int64_t)) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void **>(&p->tab_dev), 128 * sizeof(int64_t)) != hipSuccess) {
     free_plan(p);
     return fail(ATSFFT_ENOMEM, "window table allocation failed");
   }
@@ -447,7 +485,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     ok = hipMemcpy(p->G_dev, taps_all.data(), taps_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(p->Ghat_dev, ghat_all.data(), ghat_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   }
-  ok = ok && hipMemcpy(p->tab_dev, tab.data(), 96 * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(p->tab_dev, tab.data(), 128 * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && prepare_kernels(d->dtype, d->ndim, p->bucket_smem, p->est_smem, p->bwd_smem) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -476,8 +514,9 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
         const int64_t Bmin = e.ndim == 1 ? 2 : 4;
         if (e.B_max < Bmin) e.B_max = Bmin;
         if (e.B0 > e.B_max) e.B0 = e.B_max;
-      } else if (e.fixed_B > m / 2) {
-        e.fixed_B = m / 2;
+      } else {
+        if (e.fixed_B > m / 2) e.fixed_B = m / 2;
+        if (e.res_tol > 0.0 && e.B_max > m / 2) e.B_max = m / 2;
       }
       atsfft_plan_t q = nullptr;
       st = create_plan(&q, &e);
@@ -684,6 +723,8 @@ atsfft_status atsfft_trace_read(atsfft_plan_t plan, const void *ws_dev, int32_t 
   out->n_probe = s.n_probe;
   out->count = (int32_t)s.count;
   out->status = s.status;
+  out->res_ratio = s.res_ratio;
+  out->retries = s.pass;
   if (out->probe_B || out->probe_k || out->probe_dec || out->probe_T) {
     std::vector<ProbeRec> h((size_t)kMaxProbe);
     ok = hipMemcpy(h.data(), ws + lay.hist, kMaxProbe * sizeof(ProbeRec),

@@ -24,9 +24,11 @@ enum : uint32_t {
   kSigNotConverged = 2,
   kSigSaturated = 4,
   kSigEmpty = 8,
+  kSigRetried = 16,
 };
 
 enum : int { kPhaseProbe = 0, kPhaseLoc = 1, kPhaseEst = 2 };
+constexpr int kPassIter = 32;  // draw iterations of residual-test pass p start at 32 p
 
 // Per-signal control block of the adaptive probe and the vote (device memory).
 struct SigState {
@@ -39,7 +41,9 @@ struct SigState {
   uint32_t visited; // bit log2(B) set once B was probed
   int32_t n_probe;  // probe iterations run
   uint32_t count;   // |S|, appended by the vote
-  int32_t pad[7];
+  int32_t pass;     // location/estimation pass of the residual test (draw iterations + 32 pass)
+  double res_ratio; // E_res / E_tot of the last pass (residual test)
+  int32_t pad[4];
 };
 static_assert(sizeof(SigState) == 64, "SigState layout");
 
@@ -55,7 +59,7 @@ static_assert(sizeof(ProbeRec) == 32, "ProbeRec layout");
 struct Layout {
   size_t slice;
   size_t state, hist, yprobe, ymain, ymain_loop, tloc, jcount;
-  size_t jbits, jbits_loop, jlist, jlist_loop, S, tape, bflag;
+  size_t jbits, jbits_loop, jlist, jlist_loop, S, tape, bflag, resid;
   size_t total;
 };
 
@@ -73,9 +77,14 @@ struct KParams {
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
   uint64_t probe_off[kMaxProbe];       // complex offset of level i's bucket arrays in the probe area
   double q, neg_log1mq, noise_rate, rho;
+  double res_tol;        // residual test: re-run at 2 B_star above this E_res / E_tot (0: off)
+  uint32_t res_retries;  // most re-runs
+  uint32_t res_reach;    // model reach in buckets to each side of a frequency's own
+  uint32_t pass;         // the pass this launch runs (signals of other passes skip)
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
-  const int64_t *tab;  // [3][32] element offsets by log2 B: probe taps, main taps, main G'
+  const int64_t *tab;  // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),
+                       // main G'(q) for |q| <= (reach + 1) n/B (residual test)
   uint8_t *ws;
   Layout lay;
   const void *x;
@@ -103,6 +112,7 @@ hipError_t launch_backward(const KParams &P, int dtype, int batch, const void *g
 size_t bwd_smem_bytes(int dtype, uint32_t Bc_max, uint32_t max_out);
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
 size_t estimate_smem_bytes(uint32_t max_out);
+size_t residual_smem_bytes(int dtype, uint32_t Bc_max);
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);
 
 }  // namespace atsfft

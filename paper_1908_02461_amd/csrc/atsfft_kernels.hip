@@ -123,6 +123,9 @@ __device__ __forceinline__ int32_t *jlist_of(const KParams &P, uint32_t sig, uin
 __device__ __forceinline__ uint32_t *S_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.S);
 }
+__device__ __forceinline__ double *resid_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<double *>(slice_of(P, sig) + P.lay.resid);
+}
 __device__ __forceinline__ int32_t *bflag_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<int32_t *>(slice_of(P, sig) + P.lay.bflag);
 }
@@ -132,6 +135,10 @@ __device__ __forceinline__ uint16_t *tape_of(const KParams &P, uint32_t sig) {
 template <typename R>
 __device__ __forceinline__ const R *taps_of(const KParams &P, int which, uint32_t logB) {
   return reinterpret_cast<const R *>(P.G) + P.tab[which * 32 + logB];
+}
+// G'(q) for |q| <= (reach + 1) n/B, centred (residual test)
+template <typename R> __device__ __forceinline__ const R *ghat_wide_of(const KParams &P, uint32_t logB) {
+  return reinterpret_cast<const R *>(P.Ghat) + P.tab[96 + logB];
 }
 template <typename R> __device__ __forceinline__ const R *ghat_of(const KParams &P, uint32_t logB) {
   return reinterpret_cast<const R *>(P.Ghat) + P.tab[64 + logB];
@@ -269,7 +276,9 @@ __global__ void k_init(KParams P, int batch) {
   s.visited = 0;
   s.n_probe = 0;
   s.count = 0;
-  for (int i = 0; i < 7; ++i) s.pad[i] = 0;
+  s.pass = 0;
+  s.res_ratio = 0.0;
+  for (int i = 0; i < 4; ++i) s.pad[i] = 0;
   if (P.fixed) {
     s.done = 1;
     s.B_star = (int32_t)P.fixed_B;
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
     y[0] = yprobe_of<C>(P, sig, level);
     sstride = NDIM == 1 ? B : (size_t)B * B;
   } else {
-    if (st->status & kSigEmpty) return;
+    if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
     B = (uint32_t)st->B_star;
     alpha = P.alpha;
     const uint32_t loops = P.L_loc + P.L_est;
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
     for (int q = 0; q < LG; ++q) {
       const uint32_t loop = min(l0 + q, loops - 1);
       const int phase = loop < P.L_loc ? kPhaseLoc : kPhaseEst;
-      const int it = loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc);
+      const int it = (loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc)) + kPassIter * st->pass;
       d0[q] = draw(P, sig, phase, it, 0);
       d1[q] = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0[q];
       y[q] = ymain_of<C>(P, sig, loop);
@@ -626,7 +635,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     B = P.B0 << level;
     yg = yprobe_of<C>(P, sig, level);
   } else {
-    if (st->status & kSigEmpty) return;
+    if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
     B = (uint32_t)st->B_star;
     yg = ymain_of<C>(P, sig, loop);
   }
@@ -893,7 +902,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
   const uint32_t e = blockIdx.y, sig = blockIdx.z;
   SigState *st = state_of(P, sig);
-  if (st->status & kSigEmpty) return;
+  if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
+  const int it0 = kPassIter * st->pass;
   const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
   if (blockIdx.x >= ncand) return;
   const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
@@ -904,8 +914,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   const uint32_t words = (Bc + 31) >> 5;
   __shared__ uint32_t s_sig[kMaxLoops][2];
   if (threadIdx.x < L) {
-    s_sig[threadIdx.x][0] = draw(P, sig, kPhaseLoc, threadIdx.x, 0).sigma;
-    s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, threadIdx.x, 1).sigma : 0u;
+    s_sig[threadIdx.x][0] = draw(P, sig, kPhaseLoc, it0 + (int)threadIdx.x, 0).sigma;
+    s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, it0 + (int)threadIdx.x, 1).sigma : 0u;
   }
   for (uint32_t i = threadIdx.x; i < L * words; i += blockDim.x) {
     const uint32_t l = i / words, wi = i - l * words;
@@ -1065,6 +1075,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   SigState *st = state_of(P, sig);
   const SigState s = *st;
   __syncthreads();
+  if (s.pass != (int32_t)P.pass) return;
   uint32_t status = s.status;
   const bool empty = (s.status & kSigEmpty) != 0;
   const uint32_t count = empty ? 0u : s.count;
@@ -1103,11 +1114,11 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
 
   __shared__ uint32_t es[kMaxLoops][4];
   if (threadIdx.x < P.L_est) {
-    const Draw d0 = draw(P, sig, kPhaseEst, threadIdx.x, 0);
+    const Draw d0 = draw(P, sig, kPhaseEst, kPassIter * s.pass + (int)threadIdx.x, 0);
     es[threadIdx.x][0] = d0.sigma;
     es[threadIdx.x][1] = d0.tau;
     if (NDIM == 2) {
-      const Draw d1 = draw(P, sig, kPhaseEst, threadIdx.x, 1);
+      const Draw d1 = draw(P, sig, kPhaseEst, kPassIter * s.pass + (int)threadIdx.x, 1);
       es[threadIdx.x][2] = d1.sigma;
       es[threadIdx.x][3] = d1.tau;
     }
@@ -1172,6 +1183,152 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   }
 }
 
+// ------------------------------------------------------ residual test ----
+
+// A check added to the method (the paper has none): one workgroup per
+// (estimation loop, signal) of the launch's pass.  The loop's bucket DFT is
+// modelled from the located values by Lemma 1 and the fold: each f adds
+// X_f omega^{-tau f} G'(q) to the buckets h + j (|j| <= R per axis, R at most
+// (B-1)/2) around its own bucket h, with q = o + j n/B and o its offset.  The
+// model is accumulated in LDS (located frequencies sharing a bucket add with
+// atomics); E_res = sum |y_hat - M|^2 and E_tot = sum |y_hat|^2 are summed in
+// FP64 and stored per loop.
+template <typename R, int NDIM>
+__global__ __launch_bounds__(kBucketThreads) void k_residual(KParams P) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t l = blockIdx.x, sig = blockIdx.y;
+  const SigState s = *state_of(P, sig);
+  if ((s.status & kSigEmpty) || s.pass != (int32_t)P.pass) return;
+  double *res = resid_of(P, sig);
+  if (s.status & kSigTruncated) {  // no values to model: the control counts it as infinite
+    if (threadIdx.x == 0) {
+      res[l] = 0.0;
+      res[kMaxLoops + l] = 0.0;
+    }
+    return;
+  }
+  const uint32_t B = (uint32_t)s.B_star, logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
+  const uint32_t logW = logn - logB, c = (1u << logW) >> 1;
+  const int reach = (int)min(P.res_reach, (B - 1u) / 2u);
+  const int cw = (int)((P.res_reach + 1u) << logW);
+  const R *gw = ghat_wide_of<R>(P, logB) + cw;
+  const R two_over_n = (R)2 / (R)n;
+  const uint32_t tid = threadIdx.x, T = blockDim.x;
+  R *M = reinterpret_cast<R *>(smem);  // [Bc] complex, interleaved
+  double *red = reinterpret_cast<double *>(smem + (size_t)P.Bc_max * sizeof(C));
+  for (uint32_t b = tid; b < 2 * Bc; b += T) M[b] = 0;
+  __syncthreads();
+  uint32_t es[4];
+  {
+    const int it = kPassIter * s.pass + (int)l;
+    const Draw d0 = draw(P, sig, kPhaseEst, it, 0);
+    es[0] = d0.sigma;
+    es[1] = d0.tau;
+    if (NDIM == 2) {
+      const Draw d1 = draw(P, sig, kPhaseEst, it, 1);
+      es[2] = d1.sigma;
+      es[3] = d1.tau;
+    } else {
+      es[2] = es[3] = 0;
+    }
+  }
+  const int64_t *locs = P.locs + out_slot(P, sig) * P.max_out;
+  const C *vals = reinterpret_cast<const C *>(P.vals) + out_slot(P, sig) * P.max_out;
+  for (uint32_t i = tid; i < s.count; i += T) {
+    const uint32_t f = (uint32_t)locs[i];
+    const C X = vals[i];
+    const uint32_t fa[2] = {NDIM == 1 ? f : f >> logn, NDIM == 1 ? 0u : f & mask};
+    uint32_t h[2] = {0, 0};
+    int o[2] = {0, 0};
+    uint32_t phase = 0;
+#pragma unroll
+    for (int a = 0; a < NDIM; ++a) {
+      const uint32_t pa = (es[2 * a] * fa[a]) & mask;
+      h[a] = ((pa + c) & mask) >> logW;
+      const uint32_t dd = ((h[a] << logW) - pa) & mask;
+      o[a] = dd > (n >> 1) ? (int)dd - (int)n : (int)dd;
+      phase += es[2 * a + 1] * fa[a];
+    }
+    phase &= mask;
+    // X_f omega^{-tau f}, omega^{-m} = e^{+2 pi i m / n}
+    R sn, cs;
+    sincos_pi((R)phase * two_over_n, &sn, &cs);
+    const R cr = X.x * cs - X.y * sn, ci = X.x * sn + X.y * cs;
+    for (int j1 = -reach; j1 <= reach; ++j1) {
+      const R g1 = gw[o[0] + (j1 << logW)];
+      const uint32_t b1 = (h[0] + (uint32_t)j1) & (B - 1u);
+      if (NDIM == 1) {
+        atomicAdd(&M[2 * b1], cr * g1);
+        atomicAdd(&M[2 * b1 + 1], ci * g1);
+      } else {
+        for (int j2 = -reach; j2 <= reach; ++j2) {
+          const R g = g1 * gw[o[1] + (j2 << logW)];
+          const uint32_t b = (b1 << logB) | ((h[1] + (uint32_t)j2) & (B - 1u));
+          atomicAdd(&M[2 * b], cr * g);
+          atomicAdd(&M[2 * b + 1], ci * g);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const C *y = ymain_of<C>(P, sig, P.L_loc + l);
+  double er = 0.0, et = 0.0;
+  for (uint32_t b = tid; b < Bc; b += T) {
+    const C v = y[b];
+    const double dr = (double)v.x - (double)M[2 * b], di = (double)v.y - (double)M[2 * b + 1];
+    er += dr * dr + di * di;
+    et += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    er += __shfl_xor(er, off);
+    et += __shfl_xor(et, off);
+  }
+  if ((tid & 63u) == 0) {
+    red[2 * (tid >> 6)] = er;
+    red[2 * (tid >> 6) + 1] = et;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (uint32_t wv = 0; wv < (T + 63) / 64; ++wv) {
+      a += red[2 * wv];
+      b += red[2 * wv + 1];
+    }
+    res[l] = a;
+    res[kMaxLoops + l] = b;
+  }
+}
+
+// One thread per signal of the launch's pass: E_res / E_tot over the
+// estimation loops in loop order (infinite for a truncated pass); above
+// res_tol, while re-runs remain and 2 B_star <= B_max, the next pass runs
+// location and estimation at 2 B_star.
+__global__ void k_retry_control(KParams P, int batch) {
+  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sig >= batch) return;
+  SigState *st = state_of(P, (uint32_t)sig);
+  const SigState s = *st;
+  if ((s.status & kSigEmpty) || s.pass != (int32_t)P.pass) return;
+  const double *res = resid_of(P, (uint32_t)sig);
+  double er = 0.0, et = 0.0;
+  for (uint32_t l = 0; l < P.L_est; ++l) {
+    er += res[l];
+    et += res[kMaxLoops + l];
+  }
+  const double ratio = (s.status & kSigTruncated) ? (double)INFINITY : (et > 0.0 ? er / et : 0.0);
+  st->res_ratio = ratio;
+  const uint32_t B2 = 2u * (uint32_t)s.B_star;
+  if (ratio > P.res_tol && P.pass < P.res_retries && B2 <= P.B_max && B2 <= P.n / 2u) {
+    st->B_star = (int32_t)B2;
+    st->pass = s.pass + 1;
+    st->status = (s.status | kSigRetried) & ~(uint32_t)kSigTruncated;
+    st->count = 0;
+  }
+}
+
 // ------------------------------------------------------------ adjoint ----
 
 // Gradient of a real loss through the values at fixed located frequencies
@@ -1209,11 +1366,11 @@ __global__ __launch_bounds__(kBucketThreads) void k_bwd_bucket(KParams P, const 
   const R two_over_n = (R)2 / (R)n;
   uint32_t es[4];
   {
-    const Draw d0 = draw(P, sig, kPhaseEst, (int)l, 0);
+    const Draw d0 = draw(P, sig, kPhaseEst, kPassIter * s.pass + (int)l, 0);
     es[0] = d0.sigma;
     es[1] = d0.tau;
     if (NDIM == 2) {
-      const Draw d1 = draw(P, sig, kPhaseEst, (int)l, 1);
+      const Draw d1 = draw(P, sig, kPhaseEst, kPassIter * s.pass + (int)l, 1);
       es[2] = d1.sigma;
       es[3] = d1.tau;
     } else {
@@ -1304,16 +1461,17 @@ template <typename R, int NDIM>
 __global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *grad_x) {
   using C = typename CT<R>::C;
   const uint32_t sig = blockIdx.y;
-  __shared__ uint32_t s_inv[kMaxLoops][NDIM], s_tau[kMaxLoops][NDIM];
+  __shared__ uint32_t s_inv[kMaxLoops][2], s_tau[kMaxLoops][2];
   __shared__ const C *s_u[kMaxLoops];
   __shared__ uint32_t s_nl;
   const int32_t *flag = bflag_of(P, sig);
   if (threadIdx.x == 0) {
+    const int it0 = kPassIter * state_of(P, sig)->pass;
     uint32_t nl = 0;
     for (uint32_t l = 0; l < P.L_est; ++l) {
       if (!flag[l]) continue;
       for (int ax = 0; ax < NDIM; ++ax) {
-        const Draw d = draw(P, sig, kPhaseEst, (int)l, ax);
+        const Draw d = draw(P, sig, kPhaseEst, it0 + (int)l, ax);
         s_inv[nl][ax] = inv_odd(d.sigma);
         s_tau[nl][ax] = d.tau;
       }
@@ -1449,6 +1607,11 @@ size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   return fft > sel ? fft : sel;
 }
 
+size_t residual_smem_bytes(int dtype, uint32_t Bc_max) {
+  const size_t cs = dtype == 0 ? 2 * sizeof(float) : 2 * sizeof(double);
+  return cs * Bc_max + 2 * sizeof(double) * (kBucketThreads / 64);
+}
+
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max) { return 4 * (size_t)L_loc * ((Bc_max + 31) / 32); }
 
 size_t estimate_smem_bytes(uint32_t max_out) {
@@ -1463,6 +1626,11 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_bucket<R, NDIM>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd);
+  if (e != hipSuccess) return e;
+  // the residual model: B^ndim complex plus the FP64 reduction scratch, at
+  // most the bucket kernel's LDS plus 256 bytes
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_residual<R, NDIM>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bucket + 256));
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vote<NDIM>), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
@@ -1513,29 +1681,46 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     }
   }
   if (mark) mark(ctx, 1);
+  // location and estimation of one pass; Q.pass selects the signals
   const uint32_t loops = P.L_loc + P.L_est;
   const uint32_t LG = NDIM == 1 ? P.hash_loops : 1u;
   const dim3 hgrid(hash_blocks, (loops + LG - 1) / LG, batch);
-  if (NDIM == 2 || LG == 1)
-    hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
-  else if (LG == 2)
-    hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
-  else
-    hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, P, 1, 0, batch);
-  if (mark) mark(ctx, 2);
-  hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, P, 1, 0);
-  if (mark) mark(ctx, 3);
   const uint32_t E = P.L_loc - P.T_vote + 1;
   const uint32_t vote_blocks = 32;
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
-  hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, P);
-  if (mark) mark(ctx, 4);
-  if (P.L_est <= 8)
-    hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, P);
-  else if (P.L_est <= 16)
-    hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(batch), dim3(kEstThreads), esmem, s, P);
-  else
-    hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(batch), dim3(kEstThreads), esmem, s, P);
+  auto main_pass = [&](const KParams &Q, bool marks) {
+    if (NDIM == 2 || LG == 1)
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+    else if (LG == 2)
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+    else
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+    if (marks && mark) mark(ctx, 2);
+    hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
+    if (marks && mark) mark(ctx, 3);
+    hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+    if (marks && mark) mark(ctx, 4);
+    if (Q.L_est <= 8)
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+    else if (Q.L_est <= 16)
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+    else
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+  };
+  main_pass(P, true);
+  if (P.res_tol > 0.0) {
+    // residual test after every pass; a pass r > 0 runs only the signals the
+    // test sent back at 2 B_star
+    const size_t rsmem = residual_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
+    KParams Q = P;
+    for (uint32_t r = 0;; ++r) {
+      Q.pass = r;
+      if (r > 0) main_pass(Q, false);
+      hipLaunchKernelGGL((k_residual<R, NDIM>), dim3(P.L_est, batch), dim3(kBucketThreads), rsmem, s, Q);
+      hipLaunchKernelGGL(k_retry_control, dim3((batch + 255) / 256), dim3(256), 0, s, Q, batch);
+      if (r >= P.res_retries) break;
+    }
+  }
   if (mark) mark(ctx, 5);
   return hipGetLastError();
 }

@@ -24,6 +24,7 @@ def oracle_params(plan: A.Plan, signal: int = 0) -> oracle.Params:
         L_loc=d.L_loc, L_est=d.L_est, T_vote=d.T_vote, P_max=d.P_max, d=d.d, gamma=d.gamma,
         delta=d.delta, q=d.q, noise_rate=d.noise_rate, rho=d.rho, seed=d.seed, signal=signal,
         fixed_B=d.fixed_B if fixed else 0, fixed_k=d.fixed_k if fixed else 0, max_out=d.max_out,
+        res_tol=d.res_tol, res_retries=d.res_retries,
     )
 
 

@@ -48,6 +48,7 @@ def test_default_desc_values():
     dict(n=1000), dict(L_est=8), dict(L_est=33), dict(T_vote=0), dict(T_vote=10), dict(B0=48),
     dict(B0=64, B_max=32), dict(delta=0.0), dict(alpha=7), dict(max_out=0), dict(max_out=1 << 20),
     dict(P_max=0), dict(B_max=1 << 15), dict(q=1.0), dict(n=1 << 31), dict(ndim=3),
+    dict(res_tol=-1.0), dict(res_retries=8), dict(res_retries=-1),
 ])
 def test_plan_rejects_invalid_descriptors(knobs):
     lib = A.load()
@@ -65,6 +66,21 @@ def test_fixed_b_validation():
     d = A.default_desc(1, 1 << 16, "c64", fixed_B=3000)
     h = C.c_void_p()
     assert lib.atsfft_plan(C.byref(h), C.byref(d)) == A.EINVAL
+    # re-runs of the residual test grow a fixed B up to B_max, which must be valid
+    d = A.default_desc(1, 1 << 16, "c64", fixed_B=256, fixed_k=8, res_tol=1e-3, B_max=3000)
+    assert lib.atsfft_plan(C.byref(h), C.byref(d)) == A.EINVAL
+
+
+def test_descriptor_layout_matches_the_library():
+    """atsfft_default_desc writes exactly sizeof(atsfft_desc) bytes: none past
+    the binding's structure, and every field the binding declares."""
+    lib = A.load()
+    n = C.sizeof(A.Desc)
+    buf = (C.c_uint8 * (n + 64))(*([0xA5] * (n + 64)))
+    assert lib.atsfft_default_desc(C.cast(buf, C.POINTER(A.Desc)), 1, 1 << 16, A.C64) == A.SUCCESS
+    assert bytes(buf[n:]) == b"\xa5" * 64
+    d = C.cast(buf, C.POINTER(A.Desc)).contents
+    assert d.res_tol == 0.0 and d.res_retries == 1 and d.n == 1 << 16
 
 
 def test_null_arguments():
