@@ -65,7 +65,9 @@ enum {
 /* Descriptor flags. */
 enum {
   ATSFFT_FLAG_FIXED_B = 1, /* skip the probe: bucket count fixed_B, khat = fixed_k (Algorithm 1) */
-  ATSFFT_FLAG_PROFILE = 2  /* record stage timing events on every execute (atsfft_profile_read) */
+  ATSFFT_FLAG_PROFILE = 2, /* record stage timing events on every execute (atsfft_profile_read) */
+  ATSFFT_FLAG_COMPENSATED = 4 /* C64: Neumaier-compensated FP32 fold sums (the product's rounding
+                                 error from an fma), slab partials added in FP64; no effect for C128 */
 };
 
 /* Stages timed under ATSFFT_FLAG_PROFILE, in order. */

@@ -21,6 +21,7 @@ C64, C128 = 0, 1
 SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY, SIG_RETRIED = 0, 1, 2, 4, 8, 16
 FLAG_FIXED_B = 1
 FLAG_PROFILE = 2
+FLAG_COMPENSATED = 4
 STAGES = ("probe", "hash_main", "bucket_main", "vote", "estimate")
 
 
@@ -140,6 +141,7 @@ def default_desc(ndim: int, n: int, dtype: str = "c64", **knobs) -> Desc:
     _check(load().atsfft_default_desc(C.byref(d), ndim, n, C64 if dtype == "c64" else C128),
            "atsfft_default_desc")
     profile = bool(knobs.pop("profile", False))
+    compensated = bool(knobs.pop("compensated", False))
     for k, v in knobs.items():
         if not hasattr(d, k):
             raise TypeError(f"unknown knob {k!r}")
@@ -148,6 +150,8 @@ def default_desc(ndim: int, n: int, dtype: str = "c64", **knobs) -> Desc:
         d.flags |= FLAG_FIXED_B
     if profile:
         d.flags |= FLAG_PROFILE
+    if compensated:
+        d.flags |= FLAG_COMPENSATED
     return d
 
 

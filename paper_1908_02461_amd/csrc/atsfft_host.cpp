@@ -267,6 +267,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.res_retries = (uint32_t)d.res_retries;
   P.res_reach = residual_reach(&d);
   P.pass = 0;
+  P.comp = (d.flags & ATSFFT_FLAG_COMPENSATED) && d.dtype == ATSFFT_C64 ? 1u : 0u;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;

@@ -81,6 +81,7 @@ struct KParams {
   uint32_t res_retries;  // most re-runs
   uint32_t res_reach;    // model reach in buckets to each side of a frequency's own
   uint32_t pass;         // the pass this launch runs (signals of other passes skip)
+  uint32_t comp;         // FP32 fold sums compensated (Neumaier), slab partials added in FP64
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
   const int64_t *tab;  // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),

@@ -314,7 +314,27 @@ constexpr int kVoteIlp = 4;      // vote candidates tested together
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
-template <typename R, int NDIM, int LG>
+// s + c += a b with Neumaier's compensated sum: the product's rounding error
+// comes exactly from an fma and the addition's from the larger operand; the
+// explicitly rounded operations keep the compiler from contracting them.
+__device__ __forceinline__ void neumaier_fma(float &s, float &c, float a, float b) {
+  const float p = __fmul_rn(a, b);
+  const float e = fmaf(a, b, -p);
+  const float t = __fadd_rn(s, p);
+  const float d = fabsf(s) >= fabsf(p) ? __fadd_rn(__fsub_rn(s, t), p) : __fadd_rn(__fsub_rn(p, t), s);
+  c = __fadd_rn(c, __fadd_rn(d, e));
+  s = t;
+}
+__device__ __forceinline__ void neumaier_add(float &s, float &c, float v) {
+  const float t = __fadd_rn(s, v);
+  const float d = fabsf(s) >= fabsf(v) ? __fadd_rn(__fsub_rn(s, t), v) : __fadd_rn(__fsub_rn(v, t), s);
+  c = __fadd_rn(c, d);
+  s = t;
+}
+
+// COMP (FP32 only): every accumulation carries a Neumaier compensation term
+// through the wraps and the LDS reduction, and the partial is s + c.
+template <typename R, int NDIM, int LG, bool COMP = false>
 __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter, int batch) {
   using C = typename CT<R>::C;
   (void)batch;
@@ -367,12 +387,14 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
   const C *x = reinterpret_cast<const C *>(P.x) + x_offset(P, sig);
   const uint32_t bi = threadIdx.x & (kTile - 1), g = threadIdx.x >> 6;
   __shared__ R red_x[LG][4][kTile], red_y[LG][4][kTile];
+  __shared__ R red_cx[COMP ? LG : 1][COMP ? 4 : 1][COMP ? kTile : 1];
+  __shared__ R red_cy[COMP ? LG : 1][COMP ? 4 : 1][COMP ? kTile : 1];
 
   for (uint32_t tile = slot; tile * kTile < Bc; tile += nslots) {
     const uint32_t b = tile * kTile + bi;
-    R ax[LG], ay[LG];
+    R ax[LG], ay[LG], cx[LG], cy[LG];
 #pragma unroll
-    for (int q = 0; q < LG; ++q) ax[q] = ay[q] = 0;
+    for (int q = 0; q < LG; ++q) ax[q] = ay[q] = cx[q] = cy[q] = 0;
     if (b < Bc) {
       if (NDIM == 1) {
         // the group's wraps r = g, g + 4, ...: addresses advance by sigma * 4B;
@@ -406,8 +428,13 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
           for (int q = 0; q < LG; ++q) {
 #pragma unroll
             for (int u = 0; u < kHashU; ++u) {
-              ax[q] += v[q][u].x * gt[q][u];
-              ay[q] += v[q][u].y * gt[q][u];
+              if constexpr (COMP) {
+                neumaier_fma(ax[q], cx[q], v[q][u].x, gt[q][u]);
+                neumaier_fma(ay[q], cy[q], v[q][u].y, gt[q][u]);
+              } else {
+                ax[q] += v[q][u].x * gt[q][u];
+                ay[q] += v[q][u].y * gt[q][u];
+              }
             }
           }
         }
@@ -435,8 +462,13 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
             }
 #pragma unroll
             for (int u = 0; u < kHashU; ++u) {
-              ax[0] += v[u].x * gt[u];
-              ay[0] += v[u].y * gt[u];
+              if constexpr (COMP) {
+                neumaier_fma(ax[0], cx[0], v[u].x, gt[u]);
+                neumaier_fma(ay[0], cy[0], v[u].y, gt[u]);
+              } else {
+                ax[0] += v[u].x * gt[u];
+                ay[0] += v[u].y * gt[u];
+              }
             }
           }
         }
@@ -446,6 +478,10 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
     for (int q = 0; q < LG; ++q) {
       red_x[q][g][bi] = ax[q];
       red_y[q][g][bi] = ay[q];
+      if constexpr (COMP) {
+        red_cx[q][g][bi] = cx[q];
+        red_cy[q][g][bi] = cy[q];
+      }
     }
     __syncthreads();
     if (g == 0 && b < Bc) {
@@ -453,8 +489,20 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
       for (int q = 0; q < LG; ++q) {
         if ((uint32_t)q < nl) {
           C s;
-          s.x = ((red_x[q][0][bi] + red_x[q][1][bi]) + red_x[q][2][bi]) + red_x[q][3][bi];
-          s.y = ((red_y[q][0][bi] + red_y[q][1][bi]) + red_y[q][2][bi]) + red_y[q][3][bi];
+          if constexpr (COMP) {
+            R sx = red_x[q][0][bi], sy = red_y[q][0][bi], ex = red_cx[q][0][bi], ey = red_cy[q][0][bi];
+            for (int gg = 1; gg < 4; ++gg) {
+              neumaier_add(sx, ex, red_x[q][gg][bi]);
+              neumaier_add(sy, ey, red_y[q][gg][bi]);
+              ex = __fadd_rn(ex, red_cx[q][gg][bi]);
+              ey = __fadd_rn(ey, red_cy[q][gg][bi]);
+            }
+            s.x = __fadd_rn(sx, ex);
+            s.y = __fadd_rn(sy, ey);
+          } else {
+            s.x = ((red_x[q][0][bi] + red_x[q][1][bi]) + red_x[q][2][bi]) + red_x[q][3][bi];
+            s.y = ((red_y[q][0][bi] + red_y[q][1][bi]) + red_y[q][2][bi]) + red_y[q][3][bi];
+          }
           y[q][(size_t)slab * sstride + b] = s;
         }
       }
@@ -653,13 +701,26 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     } else {
       dst = (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
     }
-    // the slab partials of k_hash, added in slab order
+    // the slab partials of k_hash, added in slab order (in FP64 for the
+    // compensated FP32 fold)
     C v = yg[b];
+    if (P.comp) {
+      double vx = v.x, vy = v.y;
 #pragma unroll
-    for (int sl = 1; sl < kSlabs; ++sl) {
-      const C u = yg[(size_t)sl * sstride + b];
-      v.x += u.x;
-      v.y += u.y;
+      for (int sl = 1; sl < kSlabs; ++sl) {
+        const C u = yg[(size_t)sl * sstride + b];
+        vx += (double)u.x;
+        vy += (double)u.y;
+      }
+      v.x = (R)vx;
+      v.y = (R)vy;
+    } else {
+#pragma unroll
+      for (int sl = 1; sl < kSlabs; ++sl) {
+        const C u = yg[(size_t)sl * sstride + b];
+        v.x += u.x;
+        v.y += u.y;
+      }
     }
     buf[dst] = v;
   }
@@ -1672,8 +1733,12 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       const uint32_t Bt = P.B0 << (hi - 1);
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
       const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s, P,
-                         0, (int)lo, batch);
+      if (sizeof(R) == 4 && P.comp)
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), dim3(kSlabs * slots, hi - lo, batch),
+                           dim3(kHashThreads), 0, s, P, 0, (int)lo, batch);
+      else
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s,
+                           P, 0, (int)lo, batch);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       hipLaunchKernelGGL((k_probe_control<NDIM>), dim3((batch + 255) / 256), dim3(256), 0, s, P, (int)lo, (int)hi,
                          batch);
@@ -1685,11 +1750,14 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const uint32_t loops = P.L_loc + P.L_est;
   const uint32_t LG = NDIM == 1 ? P.hash_loops : 1u;
   const dim3 hgrid(hash_blocks, (loops + LG - 1) / LG, batch);
+  const dim3 hgrid1(hash_blocks, loops, batch);
   const uint32_t E = P.L_loc - P.T_vote + 1;
   const uint32_t vote_blocks = 32;
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   auto main_pass = [&](const KParams &Q, bool marks) {
-    if (NDIM == 2 || LG == 1)
+    if (sizeof(R) == 4 && Q.comp)
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), hgrid1, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+    else if (NDIM == 2 || LG == 1)
       hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
     else if (LG == 2)
       hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);

@@ -162,3 +162,21 @@ def test_repeat_runs_are_bitwise_identical(A):
     for u, v in zip(ra, rb):
         assert np.array_equal(u["locs"], v["locs"])
         assert np.array_equal(u["vals"], v["vals"])
+
+
+@pytest.mark.parametrize("n,k,knobs", [(1 << 22, 64, {}), (1 << 16, 16, dict(alpha=256, B_max=128))])
+def test_compensated_fold(A, n, k, knobs):
+    """ATSFFT_FLAG_COMPENSATED (Neumaier FP32 fold sums, FP64 slab partials):
+    parity with the oracle, and bucket DFTs on average no farther from it than
+    the plain FP32 fold's (measured: 6 to 12 % closer; the FP32 taps and DFT
+    bound the rest)."""
+    x = synth.planted_1d(n, k, 5, mag=("uniform", 0.5, 1.0), snr_db=30.0, dtype=np.complex64)[0]
+    means = {}
+    for comp in (False, True):
+        plan = A.Plan(1, n, "c64", seed=3, compensated=comp, **knobs)
+        out, infos = _check_batch(A, plan, [x], f"compensated={comp}")
+        ref = oracle.atsfft(x.astype(np.complex128), oracle_params(plan, 0), trace=True)
+        yr, yg = ref["yhat"], plan.trace(out["ws"], 0)["yhat"]
+        means[comp] = float(np.mean(np.abs(yg - yr) / np.max(np.abs(yr), axis=1, keepdims=True)))
+    print("mean bucket error plain / compensated", means, flush=True)
+    assert means[True] <= means[False]
