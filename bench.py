@@ -255,11 +255,22 @@ def main():
         for xi in xs1:
             plan1.execute_batched(xi, out=out1, ws=ws1)
 
-    ms_single = None
+    # the same per-signal form replayed from HIP graphs (ATSFFT_FLAG_GRAPH)
+    plan1g = A.Plan(1, n, "c64", seed=PLAN_SEED, max_batch=1, graph=True)
+    out1g = plan1g.outputs(1, dev)
+    ws1g = plan1g.workspace(1, dev)
+
+    def per_signal_graph():
+        for xi in xs1:
+            plan1g.execute_batched(xi, out=out1g, ws=ws1g)
+
+    ms_single = ms_single_graph = None
     if not args.no_per_signal:
         per_signal()
         log("per-signal form")
         ms_single = timed(per_signal, max(1, args.steps // 5), stream) / batch
+        per_signal_graph()
+        ms_single_graph = timed(per_signal_graph, max(1, args.steps // 5), stream) / batch
 
     # same-GPU dense FFT (rocFFT through torch.fft) on the same batch
     y = torch.empty_like(x)
@@ -329,6 +340,7 @@ def main():
         "atsfft_ms_per_transform": ms_step / batch,
         "speedup_vs_dense_fft": ms_dense / ms_step,
         "per_signal_ms_per_transform": ms_single,
+        "per_signal_graph_ms_per_transform": ms_single_graph,
         "k_hash_source_sha256": hash_kernel_sha256(),
         "stage_ms_per_step": stage_ms,
         "profiled_ms_per_step": ms_prof,

@@ -66,8 +66,15 @@ enum {
 enum {
   ATSFFT_FLAG_FIXED_B = 1, /* skip the probe: bucket count fixed_B, khat = fixed_k (Algorithm 1) */
   ATSFFT_FLAG_PROFILE = 2, /* record stage timing events on every execute (atsfft_profile_read) */
-  ATSFFT_FLAG_COMPENSATED = 4 /* C64: Neumaier-compensated FP32 fold sums (the product's rounding
-                                 error from an fma), slab partials added in FP64; no effect for C128 */
+  ATSFFT_FLAG_COMPENSATED = 4, /* C64: Neumaier-compensated FP32 fold sums (the product's rounding
+                                  error from an fma), slab partials added in FP64; no effect for C128 */
+  ATSFFT_FLAG_GRAPH = 8        /* atsfft_execute_batched/atsfft_execute capture their launches into a
+                                  HIP graph once per call shape (batch and the seven buffer pointers;
+                                  the last 64 shapes are kept) and replay it on the caller's stream;
+                                  the buffers' contents may change between calls.  Not with
+                                  ATSFFT_FLAG_PROFILE (EINVAL).  The plan's first call of a shape
+                                  captures on a stream of its own, so that call must not come from a
+                                  thread that is capturing another stream. */
 };
 
 /* Stages timed under ATSFFT_FLAG_PROFILE, in order. */

@@ -22,6 +22,7 @@ SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY, 
 FLAG_FIXED_B = 1
 FLAG_PROFILE = 2
 FLAG_COMPENSATED = 4
+FLAG_GRAPH = 8
 STAGES = ("probe", "hash_main", "bucket_main", "vote", "estimate")
 
 
@@ -142,6 +143,7 @@ def default_desc(ndim: int, n: int, dtype: str = "c64", **knobs) -> Desc:
            "atsfft_default_desc")
     profile = bool(knobs.pop("profile", False))
     compensated = bool(knobs.pop("compensated", False))
+    graph = bool(knobs.pop("graph", False))
     for k, v in knobs.items():
         if not hasattr(d, k):
             raise TypeError(f"unknown knob {k!r}")
@@ -152,6 +154,8 @@ def default_desc(ndim: int, n: int, dtype: str = "c64", **knobs) -> Desc:
         d.flags |= FLAG_PROFILE
     if compensated:
         d.flags |= FLAG_COMPENSATED
+    if graph:
+        d.flags |= FLAG_GRAPH
     return d
 
 

@@ -38,11 +38,22 @@ struct atsfft_plan_s {
   void *stage_host;
   size_t stage_bytes;
   hipEvent_t stage_done;
+  // ATSFFT_FLAG_GRAPH: the execute's launches captured once per call shape
+  // (batch and buffers) on a plan-owned stream, replayed on the caller's
+  struct GraphEntry {
+    int32_t batch;
+    const void *ptrs[7];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream;
 };
 
 namespace {
 
 thread_local std::string g_err = "";
+constexpr size_t kMaxGraphs = 64;  // call shapes kept per plan under ATSFFT_FLAG_GRAPH
 
 atsfft_status fail(atsfft_status s, const std::string &msg) {
   g_err = msg;
@@ -128,6 +139,8 @@ atsfft_status validate(const atsfft_desc *d) {
     if (d->P_max < 1 || d->P_max > kMaxProbe) return fail(ATSFFT_EINVAL, "P_max must be in [1, 32]");
     if (d->gamma < 0) return fail(ATSFFT_EINVAL, "gamma must be >= 0");
   }
+  if ((d->flags & ATSFFT_FLAG_GRAPH) && (d->flags & ATSFFT_FLAG_PROFILE))
+    return fail(ATSFFT_EINVAL, "ATSFFT_FLAG_GRAPH and ATSFFT_FLAG_PROFILE exclude each other");
   if (!(d->res_tol >= 0.0) || d->res_retries < 0 || d->res_retries > 7)
     return fail(ATSFFT_EINVAL, "res_tol must be >= 0 and res_retries in [0, 7]");
   if (fixed && d->res_tol > 0.0 && (!is_pow2(d->B_max) || d->B_max < Bmin || d->B_max > d->n / 2))
@@ -229,6 +242,11 @@ void free_plan(atsfft_plan_s *p) {
   if (p->G_dev) (void)hipFree(p->G_dev);
   if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
   if (p->tab_dev) (void)hipFree(p->tab_dev);
+  for (auto &g : p->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -551,6 +569,43 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
   if (ws_bytes < lay.total) return fail(ATSFFT_EINVAL, "workspace too small");
   KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev);
   const atsfft_desc &d = plan->d;
+  if (d.flags & ATSFFT_FLAG_GRAPH) {
+    const void *key[7] = {x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev};
+    atsfft_plan_s::GraphEntry *hit = nullptr;
+    for (auto &g : plan->graphs)
+      if (g.batch == batch && std::memcmp(g.ptrs, key, sizeof(key)) == 0) hit = &g;
+    if (!hit) {
+      if (plan->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(plan->graphs.front().exec);
+        (void)hipGraphDestroy(plan->graphs.front().graph);
+        plan->graphs.erase(plan->graphs.begin());
+      }
+      if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(ATSFFT_ELAUNCH, "hipStreamCreateWithFlags failed");
+      atsfft_plan_s::GraphEntry e;
+      e.batch = batch;
+      std::memcpy(e.ptrs, key, sizeof(key));
+      e.graph = nullptr;
+      e.exec = nullptr;
+      if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ATSFFT_ELAUNCH, "hipStreamBeginCapture failed");
+      const hipError_t le = launch_execute(P, d.dtype, batch, plan->cap_stream, nullptr, nullptr);
+      const hipError_t ce = hipStreamEndCapture(plan->cap_stream, &e.graph);
+      if (le != hipSuccess || ce != hipSuccess ||
+          hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        (void)hipGetLastError();
+        return fail(ATSFFT_ELAUNCH, "graph capture of the execute failed");
+      }
+      plan->graphs.push_back(e);
+      hit = &plan->graphs.back();
+    }
+    if (hipGraphLaunch(hit->exec, stream) != hipSuccess) {
+      hipError_t e = hipGetLastError();
+      return fail(ATSFFT_ELAUNCH, std::string("graph launch failed: ") + hipGetErrorString(e));
+    }
+    return ATSFFT_SUCCESS;
+  }
   std::array<hipEvent_t, 6> *rec = nullptr;
   if (d.flags & ATSFFT_FLAG_PROFILE) {
     if (plan->prof_free.empty()) {

@@ -83,6 +83,13 @@ def test_descriptor_layout_matches_the_library():
     assert d.res_tol == 0.0 and d.res_retries == 1 and d.n == 1 << 16
 
 
+def test_graph_excludes_profile():
+    lib = A.load()
+    d = A.default_desc(1, 1 << 16, "c64", graph=True, profile=True)
+    h = C.c_void_p()
+    assert lib.atsfft_plan(C.byref(h), C.byref(d)) == A.EINVAL
+
+
 def test_null_arguments():
     lib = A.load()
     assert lib.atsfft_plan(None, None) == A.EINVAL
