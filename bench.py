@@ -152,6 +152,49 @@ def cpu_baseline(desc, xs, budget_s):
             "sample": f"{done} full-size transforms (n=2^22, c64 input upcast to FP64), one thread, {el:.1f} s"}
 
 
+def _oracle_uneven_one(job):
+    """One signal of the uneven workload through the oracle (a pool worker)."""
+    import oracle
+
+    i, m, k, snr, seed = job
+    from paper_1908_02461_amd import synth
+
+    x = synth.planted_1d(m, k, seed, mag=("uniform", 0.5, 1.0), snr_db=snr)[0]
+    p = oracle.Params.defaults(1, m, seed=11, signal=i, delta=1e-6)
+    t0 = time.perf_counter()
+    oracle.atsfft(x, p, trace=False)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_uneven(budget_s, workers=None):
+    """The FP64 oracle over the uneven workload's signals, one process per
+    host core (at most 16), each signal generated on the host with the same
+    recipe (the lengths, sparsities and SNRs of the batch's first signals);
+    signals per second of wall clock over the pool.  Runs before the process
+    touches the GPU (the pool forks it)."""
+    import multiprocessing as mp
+
+    rng = np.random.Generator(np.random.PCG64(4242))  # the uneven workload's draws
+    batch = 512
+    ns = (1 << rng.integers(16, 23, size=batch)).astype(np.int64)
+    ks = np.rint(np.exp(rng.uniform(np.log(4), np.log(1024), size=batch))).astype(np.int64)
+    snrs = rng.uniform(20.0, 60.0, size=batch)
+    workers = workers or min(16, os.cpu_count() or 1)
+    jobs = [(i, int(ns[i]), int(ks[i]), float(snrs[i]), 3000 + i) for i in range(batch)]
+    done, t0 = 0, time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        for _ in pool.imap_unordered(_oracle_uneven_one, jobs[: 4 * workers * 8], chunksize=1):
+            done += 1
+            if time.perf_counter() - t0 >= budget_s:
+                pool.terminate()
+                break
+    el = time.perf_counter() - t0
+    log(f"cpu baseline: {done} signals in {el:.1f} s on {workers} processes")
+    return {"value": done / el, "unit": "transforms/s", "cores": workers, "kind": "oracle",
+            "sample": f"the first {done} signals of the uneven workload's recipe (host-generated), FP64 oracle, "
+                      f"{workers} processes, {el:.1f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,9 +218,17 @@ def main():
         sys.exit(2)
 
     if args.workload != "c2":
-        from paper_1908_02461_amd import bench_extra
+        import bench_workloads
 
-        print(json.dumps(bench_extra.run(args)), flush=True)
+        cpu = None
+        if args.workload == "c4" and not args.no_cpu_baseline:
+            # before anything touches the GPU: the pool forks this process
+            log("cpu baseline (oracle, process pool)")
+            cpu = cpu_baseline_uneven(args.cpu_seconds)
+        line = bench_workloads.run(args)
+        if cpu is not None:
+            line["cpu_baseline"] = cpu
+        print(json.dumps(line), flush=True)
         return
 
     import torch

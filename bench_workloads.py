@@ -1,6 +1,7 @@
 """Benchmarks of the workloads beyond the headline one (bench.py --workload):
-the 2D image workload, the uneven batch, and forward + adjoint.  Each returns
-one JSON-serialisable record."""
+the 2D image workload, the uneven batch, forward + adjoint, and the known-k
+comparator.  Each returns one JSON-serialisable record; bench.py adds the
+CPU baseline where it has one."""
 from __future__ import annotations
 
 import sys
@@ -122,12 +123,46 @@ def run_c4(args):
         r = plan.results(out, i)
         rec.append(float(np.mean(np.isin(planted[i], r["locs"]))))
         sat += bool(r["status"] & A.SIG_PROBE_SATURATED)
+    # the plain per-signal form: every signal through a plan of its length,
+    # one execute each; its traces give each signal's bucket count
+    plans = {m: A.Plan(1, m, "c64", seed=11, max_batch=1) for m in groups}
+    pout = {m: p1.outputs(1, x.device) for m, p1 in plans.items()}
+    pws = {m: p1.workspace(1, x.device) for m, p1 in plans.items()}
+    views1 = [x[offs[i]:offs[i] + ns[i]].view(1, int(ns[i])) for i in range(batch)]
+
+    def per_signal():
+        for i in range(batch):
+            m = int(ns[i])
+            plans[m].execute_batched(views1[i], out=pout[m], ws=pws[m])
+
+    per_signal()
+    ms_single = _timed(per_signal, max(1, args.steps // 5))
+    Bs = []
+    for i in range(batch):
+        m = int(ns[i])
+        plans[m].execute_batched(views1[i], out=pout[m], ws=pws[m])
+        Bs.append(plans[m].trace(pws[m], 0, full=False)["B_star"])
+    # touched bytes of the main loops (SURVEY d-2), each signal at the B of
+    # its per-signal run and with the draws of its index in the uneven call
+    import bench
+
+    d0 = plan.desc
+    tb = 0
+    for i in range(batch):
+        m, B = int(ns[i]), Bs[i]
+        w = min(d0.alpha * B, m)
+        L = d0.L_loc + d0.L_est
+        lines = [bench._loop_lines(d0.seed, i, 1 if l < d0.L_loc else 2, l if l < d0.L_loc else l - d0.L_loc, m, w)
+                 for l in range(L)]
+        tb += 128 * np.unique(np.concatenate(lines)).size + L * B * 8
     line = _base("sparse transforms/sec, uneven batch of 512 (n 2^16..2^22, k 4..1024)", batch / (ms / 1e3),
                  "transforms/s", args, ms,
                  {"workload": "c4_1d_c64_uneven_b512", "batch": batch, "n_range": [1 << 16, 1 << 22],
                   "k_range": [4, 1024], "snr_db_range": [20, 60], "total_gib": total * 8 / 2**30})
     line.update({"dense_fft_ms_per_batch": ms_dense, "speedup_vs_dense_fft": ms_dense / ms,
-                 "recovered_fraction": float(np.mean(rec)), "probe_saturated": sat})
+                 "recovered_fraction": float(np.mean(rec)), "probe_saturated": sat,
+                 "per_signal_ms_per_batch": ms_single, "batched_over_per_signal": ms_single / ms,
+                 "touched_bytes_per_batch": tb, "touched_gbs_per_batch_time": tb / (ms / 1e3) / 1e9})
     return line
 
 
