@@ -57,7 +57,7 @@ def _same(a, b):
 def test_graph_flag_replays_match_eager(A, knobs):
     import torch
 
-    n, batch = 1 << 14, 3
+    n, batch = 1 << 14, 5
     xs = _inputs(n, batch, 100)
     plan = A.Plan(1, n, "c64", seed=9, max_batch=batch, graph=True, **knobs)
     x = torch.empty((batch, n), dtype=torch.complex64, device="cuda")

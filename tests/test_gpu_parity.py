@@ -180,3 +180,12 @@ def test_compensated_fold(A, n, k, knobs):
         means[comp] = float(np.mean(np.abs(yg - yr) / np.max(np.abs(yr), axis=1, keepdims=True)))
     print("mean bucket error plain / compensated", means, flush=True)
     assert means[True] <= means[False]
+
+
+def test_batch_of_seven(A):
+    """A batch of seven signals of different sparsity, each against the oracle
+    with its index in the call as draw key."""
+    n = 1 << 14
+    plan = A.Plan(1, n, "c128", seed=41, max_batch=7)
+    xs = [synth.planted_1d(n, 3 + i, 500 + i, mag=("uniform", 0.5, 1.0), snr_db=35.0)[0] for i in range(7)]
+    _check_batch(A, plan, xs, "batch of seven")
