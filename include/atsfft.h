@@ -1,8 +1,7 @@
 /*
  * atsfft.h - C ABI of an MI355X (gfx950) implementation of ATSFFT, the
- * adaptive-tuning sparse FFT of Shi, Yang, Zhang and You, "ATSFFT: A Novel
- * Sparse Fast Fourier Transform Enabled With Sparsity Detection"
- * (arXiv:1908.02461).
+ * adaptive-tuning sparse FFT with sparsity detection of Shi, Yang, Zhang and
+ * You (arXiv:1908.02461).
  *
  * The library takes a signal (1D, length n) or an image (2D, N x N) whose
  * spectrum is sparse, probes the unknown sparsity k with the paper's
@@ -47,7 +46,7 @@ typedef enum atsfft_status {
   ATSFFT_ENODEVICE = 2,     /* no usable gfx950 device */
   ATSFFT_ENOMEM = 3,        /* device allocation failed */
   ATSFFT_ELAUNCH = 4,       /* a kernel launch or HIP call failed */
-  ATSFFT_ENOTSUPPORTED = 5  /* valid request this build does not provide */
+  ATSFFT_ENOTSUPPORTED = 5  /* a valid request the library does not provide */
 } atsfft_status;
 
 enum { ATSFFT_C64 = 0, ATSFFT_C128 = 1 };

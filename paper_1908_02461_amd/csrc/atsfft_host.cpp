@@ -320,7 +320,7 @@ const char *atsfft_status_string(atsfft_status s) {
     case ATSFFT_ENODEVICE: return "no usable gfx950 device";
     case ATSFFT_ENOMEM: return "device allocation failed";
     case ATSFFT_ELAUNCH: return "kernel launch or HIP call failed";
-    case ATSFFT_ENOTSUPPORTED: return "not supported by this build";
+    case ATSFFT_ENOTSUPPORTED: return "not supported by the library";
   }
   return "unknown status";
 }
