@@ -1,6 +1,6 @@
 /*
- * FP64 CPU oracle of ATSFFT (Shi, Yang, Zhang, You: "ATSFFT: A Novel Sparse
- * Fast Fourier Transform Enabled With Sparsity Detection", arXiv:1908.02461).
+ * FP64 CPU oracle of ATSFFT, the adaptive-tuning sparse FFT with sparsity
+ * detection of Shi, Yang, Zhang and You (arXiv:1908.02461).
  *
  * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
  * against a plain, slow, literal reading of the paper.  Only the test suite,
