@@ -43,7 +43,8 @@ struct SigState {
   uint32_t count;   // |S|, appended by the vote
   int32_t pass;     // location/estimation pass of the residual test (draw iterations + 32 pass)
   double res_ratio; // E_res / E_tot of the last pass (residual test)
-  int32_t pad[4];
+  uint32_t round_blocks;  // probe workgroups of the current round that have recorded their count
+  int32_t pad[3];
 };
 static_assert(sizeof(SigState) == 64, "SigState layout");
 

@@ -5,15 +5,18 @@
 //
 // One batch runs as a fixed sequence of launches on one stream:
 //   k_init                      per-signal control blocks
-//   rounds of { k_hash(probe), k_bucket(probe), k_probe_control }
+//   rounds of { k_hash(probe), k_bucket(probe) }
 //                               adaptive probe (Sec. III-A), several bucket
-//                               counts per round
+//                               counts per round; the last bucket workgroup
+//                               of a signal's round applies the B-update rule
 //   k_hash(main)                L_loc + L_est loops at the probed B
 //   k_bucket(main)              bucket DFTs; location loops also select J
 //   k_vote                      located set S (reverse hash, threshold)
 //   k_estimate                  sort S, estimate and take medians
+//   [k_residual, k_retry_control and re-run passes, with the residual test]
 // Data-dependent sizes (B, |S|) stay on the device: grids are sized for the
 // largest case and workgroups past a signal's actual extent exit at once.
+// The adjoint adds k_bwd_bucket and k_bwd_gather.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -278,7 +281,8 @@ __global__ void k_init(KParams P, int batch) {
   s.count = 0;
   s.pass = 0;
   s.res_ratio = 0.0;
-  for (int i = 0; i < 4; ++i) s.pad[i] = 0;
+  s.round_blocks = 0;
+  for (int i = 0; i < 3; ++i) s.pad[i] = 0;
   if (P.fixed) {
     s.done = 1;
     s.B_star = (int32_t)P.fixed_B;
@@ -662,6 +666,77 @@ __device__ __forceinline__ int brule(int k_prev, int k) {
   return 1;
 }
 
+// ------------------------------------------------------- probe control ----
+
+// The adaptive-B iteration (Sec. III-A, Algorithm 2) for probe levels
+// [lo, hi) of one signal, on the counts its k_bucket workgroups recorded (run
+// by the last of them to finish).  The
+// probe starts at B0 and only doubles until it stops: a halving always lands
+// on a bucket count already probed (or below the occupancy guard, or below
+// B0) and ends the probe there, so iteration i always hashes at B0 * 2^i and
+// the counts of a round can be computed before its decisions are taken.
+// Decisions: the B-update rule in exact integers (D = |k_i - k_{i-1}|: 100 D
+// < 2 k_{i-1} halves, 100 D < 5 k_{i-1} keeps, else doubles; k_{i-1} = 0 and
+// the first iteration double); a count is acted on only once B^ndim >=
+// gamma * k_i; keep stops at B; halve stops at B/2 (k-hat from B); doubling
+// past B_max stops (saturated); P_max iterations stop (not converged).
+template <int NDIM>
+__device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
+  SigState *st = state_of(P, sig);
+  SigState s = *st;
+  ProbeRec *hist = hist_of(P, sig);
+  for (int i = lo; i < hi && !s.done; ++i) {
+    ProbeRec *h = hist + i;
+    const uint32_t B = (uint32_t)s.B;
+    const uint32_t logB = ilog2(B);
+    const long long Bc = NDIM == 1 ? (long long)B : (long long)B * B;
+    const int k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int dec = i == 0 ? 1 : brule(s.k_prev, k);
+    if (P.gamma > 0 && Bc < (long long)P.gamma * (long long)k) dec = 1;
+    s.visited |= 1u << logB;
+    h->dec = dec;
+    s.n_probe = i + 1;
+    bool stop = false;
+    if (dec == 0) {
+      s.B_star = (int32_t)B;
+      s.khat = k;
+      stop = true;
+    } else if (dec < 0) {
+      const uint32_t Bh = B >> 1;
+      const long long Bhc = NDIM == 1 ? (long long)Bh : (long long)Bh * Bh;
+      s.khat = k;
+      if (Bh < P.B0 || (P.gamma > 0 && Bhc < (long long)P.gamma * (long long)k) || !(s.visited & (1u << (logB - 1))))
+        s.B_star = (int32_t)B;  // the last case cannot occur on the doubling chain
+      else
+        s.B_star = (int32_t)Bh;
+      stop = true;
+    } else {
+      if (2 * B > P.B_max) {
+        s.B_star = (int32_t)B;
+        s.khat = k;
+        s.status |= kSigSaturated;
+        stop = true;
+      } else {
+        s.B = (int32_t)(2 * B);
+      }
+    }
+    if (!stop) {
+      s.k_prev = k;
+      s.B_star = (int32_t)B;
+      s.khat = k;
+      if ((uint32_t)i + 1 >= P.P_max) {
+        s.status |= kSigNotConverged;
+        stop = true;
+      }
+    }
+    if (stop) {
+      s.done = 1;
+      if (s.khat <= 0) s.status |= kSigEmpty;
+    }
+  }
+  *st = s;
+}
+
 // ------------------------------------------------------------ k_bucket ----
 
 // One workgroup per bucket array: bucket DFT (B or B x B points) in LDS,
@@ -807,9 +882,16 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     if (tid == 0) {
       ProbeRec *h = hist_of(P, sig) + level;
       h->B = (int32_t)B;
-      h->k = (int32_t)k;
       h->dec = 0;
       h->T = Td;
+      __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the last of the round's workgroups of this signal applies the rule
+      const uint32_t prior = __hip_atomic_fetch_add(&st->round_blocks, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+      if (prior + 1u == gridDim.x) {
+        __hip_atomic_store(&st->round_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        probe_control<NDIM>(P, sig, iter, iter + (int)gridDim.x);
+      }
     }
     return;
   }
@@ -875,78 +957,6 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     jcount_of(P, sig)[loop] = (int32_t)total;
     tloc_of(P, sig)[loop] = Td;
   }
-}
-
-// ---------------------------------------------------- k_probe_control ----
-
-// The adaptive-B iteration (Sec. III-A, Algorithm 2) for probe levels
-// [lo, hi), one thread per signal, on the counts k_bucket recorded.  The
-// probe starts at B0 and only doubles until it stops: a halving always lands
-// on a bucket count already probed (or below the occupancy guard, or below
-// B0) and ends the probe there, so iteration i always hashes at B0 * 2^i and
-// the counts of a round can be computed before its decisions are taken.
-// Decisions: the B-update rule in exact integers (D = |k_i - k_{i-1}|: 100 D
-// < 2 k_{i-1} halves, 100 D < 5 k_{i-1} keeps, else doubles; k_{i-1} = 0 and
-// the first iteration double); a count is acted on only once B^ndim >=
-// gamma * k_i; keep stops at B; halve stops at B/2 (k-hat from B); doubling
-// past B_max stops (saturated); P_max iterations stop (not converged).
-template <int NDIM>
-__global__ void k_probe_control(KParams P, int lo, int hi, int batch) {
-  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sig >= batch) return;
-  SigState *st = state_of(P, (uint32_t)sig);
-  SigState s = *st;
-  ProbeRec *hist = hist_of(P, (uint32_t)sig);
-  for (int i = lo; i < hi && !s.done; ++i) {
-    ProbeRec *h = hist + i;
-    const uint32_t B = (uint32_t)s.B;
-    const uint32_t logB = ilog2(B);
-    const long long Bc = NDIM == 1 ? (long long)B : (long long)B * B;
-    const int k = h->k;
-    int dec = i == 0 ? 1 : brule(s.k_prev, k);
-    if (P.gamma > 0 && Bc < (long long)P.gamma * (long long)k) dec = 1;
-    s.visited |= 1u << logB;
-    h->dec = dec;
-    s.n_probe = i + 1;
-    bool stop = false;
-    if (dec == 0) {
-      s.B_star = (int32_t)B;
-      s.khat = k;
-      stop = true;
-    } else if (dec < 0) {
-      const uint32_t Bh = B >> 1;
-      const long long Bhc = NDIM == 1 ? (long long)Bh : (long long)Bh * Bh;
-      s.khat = k;
-      if (Bh < P.B0 || (P.gamma > 0 && Bhc < (long long)P.gamma * (long long)k) || !(s.visited & (1u << (logB - 1))))
-        s.B_star = (int32_t)B;  // the last case cannot occur on the doubling chain
-      else
-        s.B_star = (int32_t)Bh;
-      stop = true;
-    } else {
-      if (2 * B > P.B_max) {
-        s.B_star = (int32_t)B;
-        s.khat = k;
-        s.status |= kSigSaturated;
-        stop = true;
-      } else {
-        s.B = (int32_t)(2 * B);
-      }
-    }
-    if (!stop) {
-      s.k_prev = k;
-      s.B_star = (int32_t)B;
-      s.khat = k;
-      if ((uint32_t)i + 1 >= P.P_max) {
-        s.status |= kSigNotConverged;
-        stop = true;
-      }
-    }
-    if (stop) {
-      s.done = 1;
-      if (s.khat <= 0) s.status |= kSigEmpty;
-    }
-  }
-  *st = s;
 }
 
 // -------------------------------------------------------------- k_vote ----
@@ -1740,8 +1750,6 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
         hipLaunchKernelGGL((k_hash<R, NDIM, 1>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s,
                            P, 0, (int)lo, batch);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
-      hipLaunchKernelGGL((k_probe_control<NDIM>), dim3((batch + 255) / 256), dim3(256), 0, s, P, (int)lo, (int)hi,
-                         batch);
       lo = hi;
     }
   }
