@@ -28,6 +28,7 @@ struct atsfft_plan_s {
   size_t bucket_smem, est_smem, bwd_smem;
   uint32_t tile_slots;  // hash workgroups per slab and loop
   uint32_t hash_loops;  // main-pass loops per hash workgroup
+  uint32_t vote_blocks; // vote workgroups per (loop, signal)
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
@@ -274,6 +275,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.fixed = (d.flags & ATSFFT_FLAG_FIXED_B) ? 1u : 0u;
   P.fixed_B = (uint32_t)d.fixed_B;
   P.fixed_k = (uint32_t)d.fixed_k;
+  P.vote_blocks = plan->vote_blocks;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
   P.tile_slots = plan->tile_slots;
@@ -410,6 +412,11 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   if (const char *env = std::getenv("ATSFFT_TILE_SLOTS")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->tile_slots = (uint32_t)v;
+  }
+  p->vote_blocks = 0;  // by batch
+  if (const char *env = std::getenv("ATSFFT_VOTE_BLOCKS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 1024) p->vote_blocks = (uint32_t)v;
   }
   p->probe_first = 2048;
   if (const char *env = std::getenv("ATSFFT_PROBE_FIRST")) {

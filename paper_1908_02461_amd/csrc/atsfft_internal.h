@@ -73,6 +73,7 @@ struct KParams {
   uint32_t fixed_B, fixed_k;
   uint32_t tile_slots;  // hash tile slots per slab
   uint32_t hash_loops;  // main-pass loops per hash workgroup (1D: 1..3)
+  uint32_t vote_blocks;  // vote workgroups per (loop, signal)
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels

@@ -1760,7 +1760,9 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const dim3 hgrid(hash_blocks, (loops + LG - 1) / LG, batch);
   const dim3 hgrid1(hash_blocks, loops, batch);
   const uint32_t E = P.L_loc - P.T_vote + 1;
-  const uint32_t vote_blocks = 32;
+  // vote workgroups per (loop, signal): more for small batches, where the
+  // launch is latency-bound (a plan knob overrides)
+  const uint32_t vote_blocks = P.vote_blocks ? P.vote_blocks : (uint32_t)max(32, 128 / batch);
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   auto main_pass = [&](const KParams &Q, bool marks) {
     if (sizeof(R) == 4 && Q.comp)
