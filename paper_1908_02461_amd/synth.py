@@ -97,3 +97,25 @@ def planted_1d_device(n: int, k: int, seed: int, mag=None, snr_db=None, device="
         noise = torch.randn(n, generator=g, device=device) + 1j * torch.randn(n, generator=g, device=device)
         x = x + (noise * scale).to(torch.complex64)
     return x, locs, amps
+
+
+def planted_2d_device(N: int, k: int, seed: int, mag=None, snr_db=None, device="cuda"):
+    """planted_2d built on the GPU (complex64): the same recipe, with the
+    inverse DFT and the noise drawn by torch."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    locs = np.sort(rng.choice(N * N, size=k, replace=False)).astype(np.int64)
+    amps = _magnitudes(rng, k, mag) * np.exp(1j * rng.uniform(0.0, 2 * np.pi, size=k))
+    X = torch.zeros(N * N, dtype=torch.complex64, device=device)
+    X[torch.from_numpy(locs).to(device)] = torch.from_numpy(amps.astype(np.complex64)).to(device)
+    x = torch.fft.ifft2(X.view(N, N))
+    del X
+    if snr_db is not None:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+        p_sig = float(torch.mean(torch.abs(x) ** 2))
+        scale = float(np.sqrt(p_sig / (10.0 ** (snr_db / 10.0)) / 2.0))
+        x = x + (torch.randn(N, N, generator=g, device=device)
+                 + 1j * torch.randn(N, N, generator=g, device=device)).to(torch.complex64) * scale
+    return x, locs, amps
