@@ -258,7 +258,9 @@ atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *gra
 /*
  * Debug trace of one signal of the last execute that used ws_dev, copied to
  * host memory after synchronising `stream`.  Fills the scalar fields and,
- * when non-NULL, the arrays (sizes from the plan: Bc = B_max^ndim):
+ * when non-NULL, the arrays (sizes from the plan: Bc = Bm^ndim with Bm the
+ * largest bucket count of the location and estimation loops: B_max, or with
+ * ATSFFT_FLAG_FIXED_B fixed_B, max(fixed_B, B_max) when res_tol > 0):
  *   probe_B/probe_k/probe_dec  int32 [P_max], probe_T double [P_max];
  *   T_loc double [L_loc], J_count int32 [L_loc];
  *   yhat   complex (plan precision) [L_loc + L_est][Bc] (bucket DFTs at B_star);
