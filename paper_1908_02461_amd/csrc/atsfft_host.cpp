@@ -24,7 +24,7 @@ struct atsfft_plan_s {
   uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
-  int64_t *tab_dev;  // [128] element offsets by log2 B
+  int64_t tab_host[128];  // element offsets by log2 B (passed in the kernel arguments)
   size_t bucket_smem, est_smem, bwd_smem;
   uint32_t tile_slots;  // hash workgroups per slab and loop
   uint32_t hash_loops;  // main-pass loops per hash workgroup
@@ -242,7 +242,6 @@ void free_plan(atsfft_plan_s *p) {
       for (hipEvent_t e : rec) (void)hipEventDestroy(e);
   if (p->G_dev) (void)hipFree(p->G_dev);
   if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
-  if (p->tab_dev) (void)hipFree(p->tab_dev);
   for (auto &g : p->graphs) {
     (void)hipGraphExecDestroy(g.exec);
     (void)hipGraphDestroy(g.graph);
@@ -294,7 +293,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.rho = d.rho;
   P.G = plan->G_dev;
   P.Ghat = plan->Ghat_dev;
-  P.tab = plan->tab_dev;
+  std::memcpy(P.tab, plan->tab_host, sizeof(P.tab));
   P.ws = static_cast<uint8_t *>(ws_dev);
   P.lay = lay;
   P.x = x_dev;
@@ -498,8 +497,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   }
   const size_t rs = d->dtype == ATSFFT_C64 ? sizeof(float) : sizeof(double);
   if (hipMalloc(&p->G_dev, taps_all.size() * rs) != hipSuccess ||
-      hipMalloc(&p->Ghat_dev, ghat_all.size() * rs) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&p->tab_dev), 128 * sizeof(int64_t)) != hipSuccess) {
+      hipMalloc(&p->Ghat_dev, ghat_all.size() * rs) != hipSuccess) {
     free_plan(p);
     return fail(ATSFFT_ENOMEM, "window table allocation failed");
   }
@@ -511,7 +509,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     ok = hipMemcpy(p->G_dev, taps_all.data(), taps_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(p->Ghat_dev, ghat_all.data(), ghat_all.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   }
-  ok = ok && hipMemcpy(p->tab_dev, tab.data(), 128 * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+  std::memcpy(p->tab_host, tab.data(), 128 * sizeof(int64_t));
   ok = ok && prepare_kernels(d->dtype, d->ndim, p->bucket_smem, p->est_smem, p->bwd_smem) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();

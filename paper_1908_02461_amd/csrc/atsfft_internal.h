@@ -86,8 +86,9 @@ struct KParams {
   uint32_t comp;         // FP32 fold sums compensated (Neumaier), slab partials added in FP64
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
-  const int64_t *tab;  // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),
-                       // main G'(q) for |q| <= (reach + 1) n/B (residual test)
+  int64_t tab[128];    // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),
+                       // main G'(q) for |q| <= (reach + 1) n/B (residual test); in the
+                       // kernel arguments, one scalar load from the offset
   uint8_t *ws;
   Layout lay;
   const void *x;

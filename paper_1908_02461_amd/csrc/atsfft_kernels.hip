@@ -338,23 +338,23 @@ __device__ __forceinline__ void neumaier_add(float &s, float &c, float v) {
 
 // COMP (FP32 only): every accumulation carries a Neumaier compensation term
 // through the wraps and the LDS reduction, and the partial is s + c.
-template <typename R, int NDIM, int LG, bool COMP = false>
-__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase, int iter, int batch) {
+template <typename R, int NDIM, int LG, bool COMP = false, bool MAIN = true>
+__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
   using C = typename CT<R>::C;
-  (void)batch;
+  constexpr bool main_phase = MAIN;
   static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
   const uint32_t slab = blockIdx.x % kSlabs;
   const uint32_t slot = blockIdx.x / kSlabs;
   const uint32_t nslots = gridDim.x / kSlabs;
   const uint32_t sig = blockIdx.z;
-  const SigState *st = state_of(P, sig);
+  const SigState st = *state_of(P, sig);  // one 64-byte read
   uint32_t B, alpha, nl = 1;
   Draw d0[LG], d1[LG];
   C *y[LG];
   size_t sstride;
   if (!main_phase) {
     const uint32_t level = (uint32_t)iter + blockIdx.y;
-    if (st->done || level >= P.probe_levels) return;
+    if (st.done || level >= P.probe_levels) return;
     B = P.B0 << level;
     alpha = P.alpha_probe;
     d0[0] = draw(P, sig, kPhaseProbe, (int)level, 0);
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
     y[0] = yprobe_of<C>(P, sig, level);
     sstride = NDIM == 1 ? B : (size_t)B * B;
   } else {
-    if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
-    B = (uint32_t)st->B_star;
+    if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
+    B = (uint32_t)st.B_star;
     alpha = P.alpha;
     const uint32_t loops = P.L_loc + P.L_est;
     const uint32_t l0 = blockIdx.y * LG;
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int main_phase
     for (int q = 0; q < LG; ++q) {
       const uint32_t loop = min(l0 + q, loops - 1);
       const int phase = loop < P.L_loc ? kPhaseLoc : kPhaseEst;
-      const int it = (loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc)) + kPassIter * st->pass;
+      const int it = (loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc)) + kPassIter * st.pass;
       d0[q] = draw(P, sig, phase, it, 0);
       d1[q] = NDIM == 2 ? draw(P, sig, phase, it, 1) : d0[q];
       y[q] = ymain_of<C>(P, sig, loop);
@@ -1744,11 +1744,11 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
       const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
       if (sizeof(R) == 4 && P.comp)
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), dim3(kSlabs * slots, hi - lo, batch),
-                           dim3(kHashThreads), 0, s, P, 0, (int)lo, batch);
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false>), dim3(kSlabs * slots, hi - lo, batch),
+                           dim3(kHashThreads), 0, s, P, (int)lo);
       else
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1>), dim3(kSlabs * slots, hi - lo, batch), dim3(kHashThreads), 0, s,
-                           P, 0, (int)lo, batch);
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false>), dim3(kSlabs * slots, hi - lo, batch),
+                           dim3(kHashThreads), 0, s, P, (int)lo);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       lo = hi;
     }
@@ -1766,13 +1766,13 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   auto main_pass = [&](const KParams &Q, bool marks) {
     if (sizeof(R) == 4 && Q.comp)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), hgrid1, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), hgrid1, dim3(kHashThreads), 0, s, Q, 0);
     else if (NDIM == 2 || LG == 1)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     else if (LG == 2)
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     else
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, Q, 1, 0, batch);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     if (marks && mark) mark(ctx, 2);
     hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
     if (marks && mark) mark(ctx, 3);
