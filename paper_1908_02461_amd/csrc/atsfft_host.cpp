@@ -29,6 +29,7 @@ struct atsfft_plan_s {
   uint32_t tile_slots;  // hash workgroups per slab and loop
   uint32_t hash_loops;  // main-pass loops per hash workgroup
   uint32_t vote_blocks; // vote workgroups per (loop, signal)
+  uint32_t rows2d_ok;   // 2D main loops may be hashed by rows staged in LDS
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
@@ -275,6 +276,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.fixed_B = (uint32_t)d.fixed_B;
   P.fixed_k = (uint32_t)d.fixed_k;
   P.vote_blocks = plan->vote_blocks;
+  P.rows2d_ok = plan->rows2d_ok;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
   P.tile_slots = plan->tile_slots;
@@ -413,6 +415,20 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     if (v >= 1 && v <= 64) p->tile_slots = (uint32_t)v;
   }
   p->vote_blocks = 0;  // by batch
+  {
+    const uint64_t row_bytes = (uint64_t)n * (d->dtype == ATSFFT_C64 ? 8 : 16);
+    const int64_t Bm = main_bmax(d);
+    // per bucket row: a thread owns one bucket column and at most kRowTaps
+    // of its wraps; streamed: at most kSlabs row wraps (one partial each)
+    p->rows2d_ok = 0;
+    if (d->ndim == 2 && row_bytes <= kRowBytes && Bm <= kHashThreads &&
+        (int64_t)d->alpha * Bm <= (int64_t)kHashThreads * kRowTaps)
+      p->rows2d_ok = d->alpha <= kSlabs ? 2u : 1u;
+    if (const char *env = std::getenv("ATSFFT_ROWS2D")) {
+      const long v = std::strtol(env, nullptr, 10);
+      if (v >= 0 && v < (long)p->rows2d_ok) p->rows2d_ok = (uint32_t)v;
+    }
+  }
   if (const char *env = std::getenv("ATSFFT_VOTE_BLOCKS")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 1024) p->vote_blocks = (uint32_t)v;

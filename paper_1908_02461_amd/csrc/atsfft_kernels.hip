@@ -666,6 +666,195 @@ __device__ __forceinline__ int brule(int k_prev, int k) {
   return 1;
 }
 
+// ---------------------------------------------------------- 2D row hash ----
+
+// 2D main-loop hash by rows: one workgroup per (bucket row b1, loop, signal).
+// The row wraps r1 of b1 pick the rows a1 = sigma1 (b1 + r1 B - w/2) + tau1;
+// each row is staged whole in LDS with coalesced 16-byte loads.  A thread
+// owns bucket b2 = tid mod B and a share of its column wraps; the column
+// addresses and taps are the same in every row, so they stay in registers,
+// and the samples come from LDS.  The workgroup completes y[b1][.] itself
+// (rows added in order, then the column shares in group order), so there are
+// no slab partials.  Used for rows of at most kRowBytes.
+template <typename R>
+__global__ __launch_bounds__(kHashThreads) void k_hash2d_rows(KParams P) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *row = reinterpret_cast<C *>(smem);
+  const uint32_t b1 = blockIdx.x, loop = blockIdx.y, sig = blockIdx.z;
+  const SigState st = *state_of(P, sig);
+  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
+  const uint32_t B = (uint32_t)st.B_star;
+  if (b1 >= B) return;
+  const uint32_t logB = ilog2(B);
+  const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t w = min(P.alpha * B, n), half = w >> 1, wraps = w >> logB;
+  const int phase = loop < P.L_loc ? kPhaseLoc : kPhaseEst;
+  const int it = (loop < P.L_loc ? (int)loop : (int)(loop - P.L_loc)) + kPassIter * st.pass;
+  const Draw d0 = draw(P, sig, phase, it, 0), d1 = draw(P, sig, phase, it, 1);
+  const R *G = taps_of<R>(P, 1, logB);
+  const C *x = reinterpret_cast<const C *>(P.x) + x_offset(P, sig);
+  const uint32_t tid = threadIdx.x, T = blockDim.x;
+  const uint32_t b2 = tid & (B - 1u), grp = tid >> logB, ngrp = T >> logB;
+  uint32_t col[kRowTaps];
+  R gc[kRowTaps];
+#pragma unroll
+  for (int k = 0; k < kRowTaps; ++k) {
+    const uint32_t r2 = grp + (uint32_t)k * ngrp;
+    const uint32_t i2 = b2 + (min(r2, wraps - 1u) << logB);
+    col[k] = (d1.sigma * (i2 - half) + d1.tau) & mask;
+    gc[k] = r2 < wraps ? G[i2] : (R)0;
+  }
+  const uint32_t units = n * (uint32_t)sizeof(C) / 16u;  // 16-byte units per row
+  R ax = 0, ay = 0;
+  for (uint32_t r1 = 0; r1 < wraps; ++r1) {
+    const uint32_t i1 = b1 + (r1 << logB);
+    const uint32_t a1 = (d0.sigma * (i1 - half) + d0.tau) & mask;
+    const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)a1 * n);
+    float4 *dst = reinterpret_cast<float4 *>(row);
+    __syncthreads();  // the previous row has been read
+    for (uint32_t q = tid; q < units; q += T) dst[q] = src[q];
+    __syncthreads();
+    R rx = 0, ry = 0;
+#pragma unroll
+    for (int k = 0; k < kRowTaps; ++k) {
+      const C v = row[col[k]];
+      rx += gc[k] * v.x;
+      ry += gc[k] * v.y;
+    }
+    const R g1 = G[i1];
+    ax += g1 * rx;
+    ay += g1 * ry;
+  }
+  // combine the column shares of each bucket in group order
+  __syncthreads();
+  R *red = reinterpret_cast<R *>(smem);
+  red[2 * tid] = ax;
+  red[2 * tid + 1] = ay;
+  __syncthreads();
+  if (grp == 0) {
+    R sx = red[2 * tid], sy = red[2 * tid + 1];
+    for (uint32_t gq = 1; gq < ngrp; ++gq) {
+      sx += red[2 * (tid + (gq << logB))];
+      sy += red[2 * (tid + (gq << logB)) + 1];
+    }
+    C out;
+    out.x = sx;
+    out.y = sy;
+    ymain_of<C>(P, sig, loop)[(b1 << logB) | b2] = out;
+  }
+}
+
+// 2D main-loop hash streamed by rows: every input row is read once per
+// signal.  A workgroup takes kStreamRows consecutive rows a1 of one image.
+// Loop l uses row a1 iff its row wrap index i1 = sigma1^-1 (a1 - tau1) + w/2
+// (mod N) is below w; the row is staged in LDS only if some loop uses it.
+// For each such loop a group of B threads forms the row's column sums of all
+// B buckets b2 (a thread holds bucket b2's taps for every column wrap, which
+// are the same in every loop), scales them by G[i1] and writes them as
+// partial r1 = i1 / B of bucket row b1 = i1 mod B.  Every partial slot is
+// written by exactly one row and k_bucket adds a bucket's partials in r1
+// order, so the result does not depend on scheduling.  Needs w / B <= 8
+// partials and B <= the workgroup size.
+template <typename R, int U>
+__global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_inv0[2 * kMaxLoops], s_tau0[2 * kMaxLoops], s_sig1[2 * kMaxLoops], s_tau1[2 * kMaxLoops];
+  C *row = reinterpret_cast<C *>(smem);
+  const uint32_t sig = blockIdx.y;
+  const SigState st = *state_of(P, sig);
+  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
+  const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
+  const uint32_t n = P.n, mask = n - 1u;
+  const uint32_t w = min(P.alpha * B, n), half = w >> 1, wraps = w >> logB;
+  const uint32_t nloops = P.L_loc + P.L_est;
+  const uint32_t tid = threadIdx.x, T = blockDim.x;
+  if (tid < nloops) {
+    const int phase = tid < P.L_loc ? kPhaseLoc : kPhaseEst;
+    const int it = (tid < P.L_loc ? (int)tid : (int)(tid - P.L_loc)) + kPassIter * st.pass;
+    const Draw d0 = draw(P, sig, phase, it, 0), d1 = draw(P, sig, phase, it, 1);
+    s_inv0[tid] = inv_odd(d0.sigma);
+    s_tau0[tid] = d0.tau;
+    s_sig1[tid] = d1.sigma;
+    s_tau1[tid] = d1.tau;
+  }
+  const R *G = taps_of<R>(P, 1, logB);
+  const uint32_t b2 = tid & (B - 1u), grp = tid >> logB, ngrp = T >> logB;
+  R gc[kSlabs];
+#pragma unroll
+  for (int k = 0; k < kSlabs; ++k) gc[k] = (uint32_t)k < wraps ? G[b2 + ((uint32_t)k << logB)] : (R)0;
+  const float4 *xs = reinterpret_cast<const float4 *>(reinterpret_cast<const C *>(P.x) + x_offset(P, sig));
+  const uint32_t units = n * (uint32_t)sizeof(C) / 16u;  // 16-byte units per row
+  float4 *dst = reinterpret_cast<float4 *>(row);
+  __syncthreads();
+  // the loops that use row a1 (the same in every thread)
+  auto uses = [&](uint32_t a1) {
+    uint64_t m = 0;
+    if (a1 < n)
+      for (uint32_t l = 0; l < nloops; ++l) {
+        const uint32_t i1 = (s_inv0[l] * (a1 - s_tau0[l]) + half) & mask;
+        if (i1 < w) m |= 1ull << l;
+      }
+    return m;
+  };
+  // the next used row is loaded into registers while the current one is hashed
+  float4 pf[U];  // U >= the row's 16-byte units per thread
+#define ATSFFT_STREAM_FETCH(A1)                                      \
+  {                                                                  \
+    const float4 *src_ = xs + (size_t)(A1) * units;                  \
+    _Pragma("unroll") for (int k = 0; k < U; ++k) {                  \
+      const uint32_t q = tid + (uint32_t)k * T;                      \
+      pf[k] = q < units ? src_[q] : make_float4(0.f, 0.f, 0.f, 0.f); \
+    }                                                                \
+  }
+  const uint32_t a_lo = blockIdx.x * kStreamRows;
+  uint32_t rr = 0;
+  uint64_t use = 0;
+  for (; rr < kStreamRows && !(use = uses(a_lo + rr)); ++rr) {
+  }
+  if (rr < kStreamRows) ATSFFT_STREAM_FETCH(a_lo + rr);
+  while (rr < kStreamRows) {
+    const uint32_t a1 = a_lo + rr;
+    __syncthreads();  // the previous row has been read
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t q = tid + (uint32_t)k * T;
+      if (q < units) dst[q] = pf[k];
+    }
+    __syncthreads();
+    const uint64_t cur = use;
+    use = 0;
+    for (++rr; rr < kStreamRows && !(use = uses(a_lo + rr)); ++rr) {
+    }
+    if (rr < kStreamRows) ATSFFT_STREAM_FETCH(a_lo + rr);
+    // the j-th loop of the row goes to group j mod ngrp
+    uint32_t j = 0;
+    for (uint64_t u = cur; u; u &= u - 1ull, ++j) {
+      if (j % ngrp != grp) continue;
+      const uint32_t l = (uint32_t)__ffsll((unsigned long long)u) - 1u;
+      const uint32_t i1 = (s_inv0[l] * (a1 - s_tau0[l]) + half) & mask;
+      const uint32_t sg = s_sig1[l], tu = s_tau1[l];
+      R rx = 0, ry = 0;
+#pragma unroll
+      for (int k = 0; k < kSlabs; ++k) {
+        if ((uint32_t)k < wraps) {
+          const uint32_t i2 = b2 + ((uint32_t)k << logB);
+          const C v = row[(sg * (i2 - half) + tu) & mask];
+          rx += gc[k] * v.x;
+          ry += gc[k] * v.y;
+        }
+      }
+      const R g1 = G[i1];
+      C out;
+      out.x = g1 * rx;
+      out.y = g1 * ry;
+      ymain_of<C>(P, sig, l)[(size_t)(i1 >> logB) * P.Bc_max + (((i1 & (B - 1u)) << logB) | b2)] = out;
+    }
+  }
+}
+#undef ATSFFT_STREAM_FETCH
+
 // ------------------------------------------------------- probe control ----
 
 // The adaptive-B iteration (Sec. III-A, Algorithm 2) for probe levels
@@ -779,7 +968,21 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     // the slab partials of k_hash, added in slab order (in FP64 for the
     // compensated FP32 fold)
     C v = yg[b];
-    if (P.comp) {
+    if (main_phase && P.rows2d == 1) {
+      // the row hash completed the bucket sums: nothing to add
+    } else if (main_phase && P.rows2d == 2) {
+      // the streamed row hash leaves one partial per row wrap; the slots
+      // past the last wrap are read (they lie in the array) but not used
+      const uint32_t nsl = min(P.alpha * B, P.n) >> logB;
+      C u[kSlabs];
+#pragma unroll
+      for (int sl = 1; sl < kSlabs; ++sl) u[sl] = yg[(size_t)sl * sstride + b];
+#pragma unroll
+      for (int sl = 1; sl < kSlabs; ++sl) {
+        v.x += (uint32_t)sl < nsl ? u[sl].x : (R)0;
+        v.y += (uint32_t)sl < nsl ? u[sl].y : (R)0;
+      }
+    } else if (P.comp) {
       double vx = v.x, vy = v.y;
 #pragma unroll
       for (int sl = 1; sl < kSlabs; ++sl) {
@@ -1703,6 +1906,15 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_residual<R, NDIM>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bucket + 256));
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hash2d_rows<R>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowBytes);
+  if (e != hipSuccess) return e;
+  for (const void *f : {reinterpret_cast<const void *>(&k_hash2d_stream<R, 4>),
+                        reinterpret_cast<const void *>(&k_hash2d_stream<R, 8>),
+                        reinterpret_cast<const void *>(&k_hash2d_stream<R, 16>)}) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowBytes);
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vote<NDIM>), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
   if (e != hipSuccess) return e;
@@ -1722,6 +1934,12 @@ hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_s
                      : set_smem<float, 2>(bucket_smem, est_smem, bwd_smem);
   return ndim == 1 ? set_smem<double, 1>(bucket_smem, est_smem, bwd_smem)
                    : set_smem<double, 2>(bucket_smem, est_smem, bwd_smem);
+}
+
+static uint32_t ilog2_host_u32(uint32_t v) {
+  uint32_t r = 0;
+  while (v >>= 1) ++r;
+  return r;
 }
 
 template <typename R, int NDIM>
@@ -1764,8 +1982,27 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   // launch is latency-bound (a plan knob overrides)
   const uint32_t vote_blocks = P.vote_blocks ? P.vote_blocks : (uint32_t)max(32, 128 / batch);
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
-  auto main_pass = [&](const KParams &Q, bool marks) {
-    if (sizeof(R) == 4 && Q.comp)
+  // 2D rows staged in LDS when the row fits and the input is 16-byte aligned
+  const size_t rows_smem = std::max<size_t>((size_t)P.n * sizeof(typename CT<R>::C), 2 * kHashThreads * sizeof(R));
+  const bool rows = NDIM == 2 && P.rows2d_ok && !P.x_off && (reinterpret_cast<uintptr_t>(P.x) & 15u) == 0 && !P.comp;
+  const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
+  auto main_pass = [&](const KParams &Q0, bool marks) {
+    KParams Q = Q0;
+    Q.rows2d = row_mode;
+    if (row_mode == 2) {
+      const dim3 sgrid((P.n + kStreamRows - 1) / kStreamRows, batch);
+      const size_t rb = (size_t)P.n * sizeof(typename CT<R>::C);
+      if (rb <= 16u * 4u * kHashThreads)
+        hipLaunchKernelGGL((k_hash2d_stream<R, 4>), sgrid, dim3(kHashThreads), rb, s, Q);
+      else if (rb <= 16u * 8u * kHashThreads)
+        hipLaunchKernelGGL((k_hash2d_stream<R, 8>), sgrid, dim3(kHashThreads), rb, s, Q);
+      else
+        hipLaunchKernelGGL((k_hash2d_stream<R, 16>), sgrid, dim3(kHashThreads), rb, s, Q);
+    }
+    else if (row_mode == 1)
+      hipLaunchKernelGGL((k_hash2d_rows<R>), dim3(1u << (ilog2_host_u32(P.Bc_max) / 2), loops, batch),
+                         dim3(kHashThreads), rows_smem, s, Q);
+    else if (sizeof(R) == 4 && Q.comp)
       hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), hgrid1, dim3(kHashThreads), 0, s, Q, 0);
     else if (NDIM == 2 || LG == 1)
       hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 0);

@@ -189,3 +189,27 @@ def test_batch_of_seven(A):
     plan = A.Plan(1, n, "c128", seed=41, max_batch=7)
     xs = [synth.planted_1d(n, 3 + i, 500 + i, mag=("uniform", 0.5, 1.0), snr_db=35.0)[0] for i in range(7)]
     _check_batch(A, plan, xs, "batch of seven")
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("N,dt,knobs", [
+    (512, "c64", dict(B_max=32)),                 # w = 8B < N: eight row wraps
+    (256, "c128", dict(fixed_B=64, fixed_k=6)),   # w = N: four row wraps
+    (512, "c64", dict(alpha=12, B_max=32)),       # alpha above 8: no streamed form
+    (4096, "c128", dict(B_max=16)),               # 64 KiB rows, the largest staged
+])
+def test_2d_main_hash_forms(A, monkeypatch, form, N, dt, knobs):
+    """The 2D main-loop hash in each of its forms (ATSFFT_ROWS2D: 0 the
+    slab gather, 1 one workgroup per bucket row, 2 rows streamed once; a plan
+    falls back to the lower form where the higher does not apply) against the
+    oracle, and bitwise repeatable."""
+    monkeypatch.setenv("ATSFFT_ROWS2D", str(form))
+    plan = A.Plan(2, N, dt, seed=13, max_batch=2, **knobs)
+    npdt = np.complex128 if dt == "c128" else np.complex64
+    xs = [synth.planted_2d(N, 6, 70 + s, mag=("uniform", 0.5, 1.0), snr_db=40.0, dtype=npdt)[0]
+          for s in range(2)]
+    out, _ = _check_batch(A, plan, xs, f"2d form {form} {N} {dt} {knobs}")
+    again = run_gpu(plan, np.stack(xs))
+    for i in range(2):
+        u, v = plan.results(out, i), plan.results(again, i)
+        assert np.array_equal(u["locs"], v["locs"]) and np.array_equal(u["vals"], v["vals"])
