@@ -65,27 +65,43 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hash_main_c2_n4m_k64_b32_hbm_traf
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_02461_amd", "csrc", "atsfft_kernels.hip")
 
 
-def hash_kernel_sha256():
-    """SHA-256 of the k_hash section of the kernel source."""
+def section_sha256(first, last):
+    """SHA-256 of the kernel source from the divider titled `first` up to the
+    one titled `last`."""
     import hashlib
 
     src = open(KERNEL_SRC).read()
-    a = src.index("// " + "-" * 61 + " k_hash ----")
-    b = src.index("// " + "-" * 57 + " LDS FFT ----")
+    lines = src.splitlines(keepends=True)
+    pos, a, b = 0, None, None
+    for ln in lines:
+        if ln.startswith("// ---") and ln.rstrip().endswith(" ----"):
+            title = ln.rstrip()[:-5].lstrip("/ -")
+            if title == first and a is None:
+                a = pos
+            elif title == last and a is not None:
+                b = pos
+                break
+        pos += len(ln)
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(batch):
-    """HBM bytes per main-hash launch from the committed counter summary, if
-    it was taken on the current k_hash source and batch; otherwise None."""
+def hash_kernel_sha256():
+    """SHA-256 of the k_hash section of the kernel source."""
+    return section_sha256("k_hash", "LDS FFT")
+
+
+def measured_traffic(batch, path=None, sha=None, key="k_hash_source_sha256"):
+    """HBM bytes per launch from a committed counter summary (default: the 1D
+    main-loop k_hash), if it was taken on the current source section and
+    batch; otherwise None."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             for line in fh:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("k_hash_source_sha256") != hash_kernel_sha256() or int(kv.get("batch", -1)) != batch:
+        if kv.get(key) != (sha or hash_kernel_sha256()) or int(kv.get("batch", -1)) != batch:
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -195,6 +211,17 @@ def cpu_baseline_uneven(budget_s, workers=None):
                       f"{workers} processes, {el:.1f} s wall"}
 
 
+def copy_calibration():
+    """One plain 1 GiB device copy: the reference for the HBM byte counters."""
+    import torch
+
+    src = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +255,8 @@ def main():
         line = bench_workloads.run(args)
         if cpu is not None:
             line["cpu_baseline"] = cpu
+        if args.copy_calibration:
+            copy_calibration()
         print(json.dumps(line), flush=True)
         return
 
@@ -352,11 +381,7 @@ def main():
         recovered.append(float(np.mean(hit)))
 
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
 
     cpu = None
     if not args.no_cpu_baseline:

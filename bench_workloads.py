@@ -4,6 +4,7 @@ comparator.  Each returns one JSON-serialisable record; bench.py adds the
 CPU baseline where it has one."""
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -67,7 +68,58 @@ def run_c3(args):
     line.update({"dense_fft2_ms_per_transform": ms_dense / batch, "speedup_vs_dense_fft2": ms_dense / ms,
                  "recovered_fraction": float(np.mean(rec)),
                  "B_star": sorted({plan.trace(ws, i, full=False)["B_star"] for i in range(batch)})})
+    # roofline of the dominant kernel, the 2D main-loop hash (streamed rows),
+    # timed with HIP events at the plan's stage marks on the library stream
+    prof = A.Plan(2, N, "c64", seed=7, max_batch=batch, profile=True)
+    pws = prof.workspace(batch, x.device)
+    pout = prof.outputs(batch, x.device)
+    for _ in range(max(1, args.warmup)):
+        prof.execute_batched(x, out=pout, ws=pws)
+    torch.cuda.synchronize()
+    prof.profile_read()
+    for _ in range(args.steps):
+        prof.execute_batched(x, out=pout, ws=pws)
+    pr = prof.profile_read()
+    stages = {kk: v / pr["executes"] for kk, v in pr.items() if kk != "executes"}
+    alg = hash2d_stream_bytes(prof.desc, [prof.trace(pws, i, full=False) for i in range(batch)])
+    hms = stages["hash_main"]
+    from bench import ROOT, measured_traffic, section_sha256
+
+    traffic = measured_traffic(batch, os.path.join(ROOT, "profiles", "hash2d_stream_c3_n4096_k256_b8_hbm_traffic.txt"),
+                               section_sha256("2D row hash", "probe control"), key="section_sha256")
+    line["roofline"] = {"bound": "hbm", "achieved": alg / (hms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": alg / (hms * 1e-3) / 8e12, "traffic": traffic,
+                        "kernel": "k_hash2d_stream (main loops)", "alg_bytes_per_launch": alg,
+                        "avg_launch_ms": hms}
+    line["stage_ms_per_step"] = stages
+    prof.close()
     return line
+
+
+def hash2d_stream_bytes(desc, trs):
+    """Bytes the streamed 2D main-loop hash must move per batch: every row
+    some loop uses, read once (N c64 samples), plus one B x B partial per row
+    wrap and loop written.  Loop l uses rows sigma1 (i1 - w/2) + tau1 mod N,
+    i1 < w, with (sigma1, tau1) drawn as the library documents."""
+    from bench import _splitmix64_at
+
+    from paper_1908_02461_amd import atsfft as A
+
+    N, L = desc.n, desc.L_loc + desc.L_est
+    total = 0
+    for s, t in enumerate(trs):
+        if t["status"] & A.SIG_EMPTY:
+            continue
+        B = t["B_star"]
+        w = min(desc.alpha * B, N)
+        rows = []
+        for l in range(L):
+            phase, it = (1, l) if l < desc.L_loc else (2, l - desc.L_loc)
+            r = _splitmix64_at(desc.seed, ((s * 4 + phase) * 256 + it) * 2)
+            sigma, tau = (r % N) | 1, (r >> 32) % N
+            rows.append((sigma * (np.arange(w, dtype=np.int64) - w // 2) + tau) % N)
+        total += np.unique(np.concatenate(rows)).size * N * 8 + L * (w // B) * B * B * 8
+    return int(total)
 
 
 def run_c4(args):

@@ -30,6 +30,7 @@ struct atsfft_plan_s {
   uint32_t hash_loops;  // main-pass loops per hash workgroup
   uint32_t vote_blocks; // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;   // 2D main loops may be hashed by rows staged in LDS
+  uint32_t stream_rows; // 2D streamed row hash: rows per workgroup
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
@@ -277,6 +278,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.fixed_k = (uint32_t)d.fixed_k;
   P.vote_blocks = plan->vote_blocks;
   P.rows2d_ok = plan->rows2d_ok;
+  P.stream_rows = plan->stream_rows;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
   P.tile_slots = plan->tile_slots;
@@ -428,6 +430,11 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
       const long v = std::strtol(env, nullptr, 10);
       if (v >= 0 && v < (long)p->rows2d_ok) p->rows2d_ok = (uint32_t)v;
     }
+  }
+  p->stream_rows = 2;  // measured at 4096^2 c64: 2 rows 249 us, 8 rows 265, 32 rows 271
+  if (const char *env = std::getenv("ATSFFT_STREAM_ROWS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 64) p->stream_rows = (uint32_t)v;
   }
   if (const char *env = std::getenv("ATSFFT_VOTE_BLOCKS")) {
     const long v = std::strtol(env, nullptr, 10);

@@ -19,7 +19,6 @@ constexpr int kGatherThreads = 256;  // adjoint gather: threads per block
 constexpr int kGatherPer = 4;        // addresses per thread and pass
 constexpr int kRowTaps = 8;                // 2D row hash: column wraps per thread, at most
 constexpr uint32_t kRowBytes = 64u << 10;  // 2D row hash: largest row staged in LDS
-constexpr uint32_t kStreamRows = 8;        // 2D streamed row hash: rows per workgroup
 constexpr int kMaxOut = 16384;
 
 enum : uint32_t {
@@ -79,6 +78,7 @@ struct KParams {
   uint32_t vote_blocks;  // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;    // 2D main-loop hash by rows allowed: 0 no, 1 per bucket row, 2 streamed (plan)
   uint32_t rows2d;       // the form this launch sequence uses (0, 1 or 2)
+  uint32_t stream_rows;  // streamed form: rows per workgroup
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels

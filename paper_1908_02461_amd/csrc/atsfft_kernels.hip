@@ -746,7 +746,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_rows(KParams P) {
 }
 
 // 2D main-loop hash streamed by rows: every input row is read once per
-// signal.  A workgroup takes kStreamRows consecutive rows a1 of one image.
+// signal.  A workgroup takes P.stream_rows consecutive rows a1 of one image.
 // Loop l uses row a1 iff its row wrap index i1 = sigma1^-1 (a1 - tau1) + w/2
 // (mod N) is below w; the row is staged in LDS only if some loop uses it.
 // For each such loop a group of B threads forms the row's column sums of all
@@ -808,13 +808,13 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
       pf[k] = q < units ? src_[q] : make_float4(0.f, 0.f, 0.f, 0.f); \
     }                                                                \
   }
-  const uint32_t a_lo = blockIdx.x * kStreamRows;
+  const uint32_t nrows = P.stream_rows, a_lo = blockIdx.x * nrows;
   uint32_t rr = 0;
   uint64_t use = 0;
-  for (; rr < kStreamRows && !(use = uses(a_lo + rr)); ++rr) {
+  for (; rr < nrows && !(use = uses(a_lo + rr)); ++rr) {
   }
-  if (rr < kStreamRows) ATSFFT_STREAM_FETCH(a_lo + rr);
-  while (rr < kStreamRows) {
+  if (rr < nrows) ATSFFT_STREAM_FETCH(a_lo + rr);
+  while (rr < nrows) {
     const uint32_t a1 = a_lo + rr;
     __syncthreads();  // the previous row has been read
 #pragma unroll
@@ -825,9 +825,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
     __syncthreads();
     const uint64_t cur = use;
     use = 0;
-    for (++rr; rr < kStreamRows && !(use = uses(a_lo + rr)); ++rr) {
+    for (++rr; rr < nrows && !(use = uses(a_lo + rr)); ++rr) {
     }
-    if (rr < kStreamRows) ATSFFT_STREAM_FETCH(a_lo + rr);
+    if (rr < nrows) ATSFFT_STREAM_FETCH(a_lo + rr);
     // the j-th loop of the row goes to group j mod ngrp
     uint32_t j = 0;
     for (uint64_t u = cur; u; u &= u - 1ull, ++j) {
@@ -1990,7 +1990,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     KParams Q = Q0;
     Q.rows2d = row_mode;
     if (row_mode == 2) {
-      const dim3 sgrid((P.n + kStreamRows - 1) / kStreamRows, batch);
+      const dim3 sgrid((P.n + P.stream_rows - 1) / P.stream_rows, batch);
       const size_t rb = (size_t)P.n * sizeof(typename CT<R>::C);
       if (rb <= 16u * 4u * kHashThreads)
         hipLaunchKernelGGL((k_hash2d_stream<R, 4>), sgrid, dim3(kHashThreads), rb, s, Q);
