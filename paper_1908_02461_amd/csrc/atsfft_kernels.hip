@@ -1169,11 +1169,24 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
 // first E = L_loc - T_vote + 1 loops, so the candidates are the preimages of
 // those loops' selected buckets; a candidate is emitted only by the first of
 // those loops that holds it, which makes S duplicate-free with no sort and
-// no n-sized histogram.  The cutoff bitmaps sit in LDS; a candidate stops
-// being tested once the loops left cannot lift it to T_vote.
-template <int NDIM>
+// no n-sized histogram.  The cutoff bitmaps sit in LDS.
+//
+// A candidate of loop e has one vote; it is tested against the other loops in
+// index order, and after m tests with v hits it can still reach T_vote only
+// if v >= m - (L_loc - T_vote).  No candidate can fail before the first
+// L_loc - T_vote + 1 tests, so those run for every candidate without
+// branches, kVoteIlp candidates per thread; the few candidates still alive
+// then go through an LDS queue, so that the remaining tests, which stop at
+// the first hopeless miss, run only on them.  SMALL: every hash product fits
+// 24-bit operands (1D n <= 2^24, and 2D), so the full-rate 24-bit multiply
+// gives the product modulo n.
+template <int NDIM, bool SMALL>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
+  constexpr int K = kVoteIlp;
+  __shared__ uint32_t s_qf[kVoteThreads * K];
+  __shared__ uint8_t s_qv[kVoteThreads * K];
+  __shared__ uint32_t s_qn;
   const uint32_t e = blockIdx.y, sig = blockIdx.z;
   SigState *st = state_of(P, sig);
   if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
@@ -1186,11 +1199,14 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
   const uint32_t L = P.L_loc, Tv = P.T_vote;
   const uint32_t words = (Bc + 31) >> 5;
+  // tests before a candidate can fail; the slack of misses it may take
+  const uint32_t slack = L - Tv, nA = min(slack + 1u, L - 1u);
   __shared__ uint32_t s_sig[kMaxLoops][2];
   if (threadIdx.x < L) {
     s_sig[threadIdx.x][0] = draw(P, sig, kPhaseLoc, it0 + (int)threadIdx.x, 0).sigma;
     s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, it0 + (int)threadIdx.x, 1).sigma : 0u;
   }
+  if (threadIdx.x == 0) s_qn = 0;
   for (uint32_t i = threadIdx.x; i < L * words; i += blockDim.x) {
     const uint32_t l = i / words, wi = i - l * words;
     s_bits[i] = jbits_of(P, sig, l)[wi];
@@ -1201,79 +1217,81 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   const uint32_t inv1 = NDIM == 2 ? (inv_odd(s_sig[e][1]) & mask) : 0u;
   uint32_t *S = S_of(P, sig);
 
+  auto mulmod = [&](uint32_t a, uint32_t b) -> uint32_t { return (SMALL ? __umul24(a, b) : a * b) & mask; };
   auto bucket = [&](uint32_t l, uint32_t f) -> uint32_t {
-    if (NDIM == 1) return ((s_sig[l][0] * f + c) & mask) >> logW;
+    if (NDIM == 1) return ((mulmod(s_sig[l][0], f) + c) & mask) >> logW;
     const uint32_t f1 = f >> logn, f2 = f & mask;
-    const uint32_t h1 = ((s_sig[l][0] * f1 + c) & mask) >> logW;
-    const uint32_t h2 = ((s_sig[l][1] * f2 + c) & mask) >> logW;
+    const uint32_t h1 = ((mulmod(s_sig[l][0], f1) + c) & mask) >> logW;
+    const uint32_t h2 = ((mulmod(s_sig[l][1], f2) + c) & mask) >> logW;
     return (h1 << logB) | h2;
   };
   auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t { return (s_bits[l * words + (h >> 5)] >> (h & 31u)) & 1u; };
-  // Candidates are tested kVoteIlp at a time so that their bitmap lookups
-  // overlap.  Loop e holds each candidate by construction; the others are
-  // counted until no candidate of the group can still reach the threshold.
-  constexpr int K = kVoteIlp;
-  auto vote_group = [&](const uint32_t (&f)[K], const bool (&valid)[K]) {
-    uint32_t votes[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) votes[k] = valid[k] ? 1u : 0u;
-    uint32_t left = L - 1;
-    for (uint32_t l = 0; l < L; ++l) {
-      if (l == e) continue;
-      bool live = false;
-#pragma unroll
-      for (int k = 0; k < K; ++k) live |= valid[k] && votes[k] + left >= Tv;
-      if (!live) return;
-      uint32_t h[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) h[k] = bucket(l, f[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) votes[k] += in_J(l, h[k]);
-      --left;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (!valid[k] || votes[k] < Tv) continue;
-      bool earlier = false;
-      for (uint32_t e2 = 0; e2 < e && !earlier; ++e2) earlier = in_J(e2, bucket(e2, f[k])) != 0u;
-      if (earlier) continue;  // emitted by an earlier loop
-      const uint32_t pos = atomicAdd(&st->count, 1u);
-      if (pos < P.max_out) S[pos] = f[k];
-    }
+  // the m-th loop other than e
+  auto other = [&](uint32_t m) -> uint32_t { return m < e ? m : m + 1u; };
+  // a candidate with all its votes counted: emitted unless an earlier
+  // candidate loop also holds it
+  auto emit = [&](uint32_t f) {
+    for (uint32_t e2 = 0; e2 < e; ++e2)
+      if (in_J(e2, bucket(e2, f))) return;
+    const uint32_t pos = atomicAdd(&st->count, 1u);
+    if (pos < P.max_out) S[pos] = f;
   };
 
   const uint32_t T = blockDim.x;
+  const uint32_t per = NDIM == 1 ? W : W * W;  // candidates per selected bucket
   for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
     const uint32_t j = (uint32_t)jl[jj];
-    if (NDIM == 1) {
-      const uint32_t p0 = (j << logW) - c;
-      for (uint32_t i0 = threadIdx.x; i0 < W; i0 += K * T) {
-        uint32_t f[K];
-        bool valid[K];
+    const uint32_t p01 = ((NDIM == 1 ? j : (j >> logB)) << logW) - c;
+    const uint32_t p02 = ((j & (B - 1u)) << logW) - c;
+    for (uint32_t base = 0; base < per; base += K * T) {
+      // the block's candidates and their first nA tests
+      uint32_t f[K], v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const uint32_t idx = i0 + (uint32_t)k * T;
-          valid[k] = idx < W;
-          f[k] = (inv0 * ((p0 + idx) & mask)) & mask;
-        }
-        vote_group(f, valid);
-      }
-    } else {
-      const uint32_t j1 = j >> logB, j2 = j & (B - 1u);
-      const uint32_t p01 = (j1 << logW) - c, p02 = (j2 << logW) - c;
-      for (uint32_t i0 = threadIdx.x; i0 < W * W; i0 += K * T) {
-        uint32_t f[K];
-        bool valid[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const uint32_t idx = i0 + (uint32_t)k * T;
-          valid[k] = idx < W * W;
+      for (int k = 0; k < K; ++k) {
+        const uint32_t idx = base + threadIdx.x + (uint32_t)k * T;
+        v[k] = idx < per ? 0u : 0x80000000u;  // the high bit marks no candidate
+        if (NDIM == 1) {
+          f[k] = mulmod(inv0, (p01 + idx) & mask);
+        } else {
           const uint32_t p1 = (p01 + (idx >> logW)) & mask;
           const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
-          f[k] = (((inv0 * p1) & mask) << logn) | ((inv1 * p2) & mask);
+          f[k] = (mulmod(inv0, p1) << logn) | mulmod(inv1, p2);
         }
-        vote_group(f, valid);
       }
+      for (uint32_t m = 0; m < nA; ++m) {
+        const uint32_t l = other(m);
+        uint32_t h[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) h[k] = bucket(l, f[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += in_J(l, h[k]);
+      }
+      // alive: v >= nA - slack (and a real candidate)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (v[k] + slack >= nA && v[k] < 0x80000000u) {
+          if (nA == L - 1u) {
+            if (1u + v[k] >= Tv) emit(f[k]);
+          } else {
+            const uint32_t q = atomicAdd(&s_qn, 1u);
+            s_qf[q] = f[k];
+            s_qv[q] = (uint8_t)v[k];
+          }
+        }
+      }
+      __syncthreads();
+      const uint32_t qn = s_qn;
+      for (uint32_t q = threadIdx.x; q < qn; q += T) {
+        const uint32_t fq = s_qf[q];
+        uint32_t vq = s_qv[q];
+        uint32_t m = nA;
+        for (; m < L - 1u && vq + slack >= m; ++m) vq += in_J(other(m), bucket(other(m), fq));
+        if (vq + slack >= m && 1u + vq >= Tv) emit(fq);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) s_qn = 0;
+      // the next block's pushes come after this barrier
+      __syncthreads();
     }
   }
 }
@@ -1915,9 +1933,12 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowBytes);
     if (e != hipSuccess) return e;
   }
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vote<NDIM>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
-  if (e != hipSuccess) return e;
+  for (const void *f : {reinterpret_cast<const void *>(&k_vote<NDIM, true>),
+                        reinterpret_cast<const void *>(&k_vote<NDIM, false>)}) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(4 * (kMaxLoops - 1) * (kBucketThreads * kBucketMaxPer / 32)));
+    if (e != hipSuccess) return e;
+  }
   const void *ks[3] = {reinterpret_cast<const void *>(&k_estimate<R, NDIM, 8>),
                        reinterpret_cast<const void *>(&k_estimate<R, NDIM, 16>),
                        reinterpret_cast<const void *>(&k_estimate<R, NDIM, 32>)};
@@ -2013,7 +2034,10 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     if (marks && mark) mark(ctx, 2);
     hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
     if (marks && mark) mark(ctx, 3);
-    hipLaunchKernelGGL((k_vote<NDIM>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+    if (NDIM == 2 || P.logn <= 24)
+      hipLaunchKernelGGL((k_vote<NDIM, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+    else
+      hipLaunchKernelGGL((k_vote<NDIM, false>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
     if (marks && mark) mark(ctx, 4);
     if (Q.L_est <= 8)
       hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
