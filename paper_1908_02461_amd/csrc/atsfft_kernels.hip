@@ -204,14 +204,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
   return r;
 }
 
-// The k-th smallest (0-based) of m[0..cnt) in LDS, by most-significant-digit
-// radix selection on the bit patterns (the values are non-negative, so their
-// patterns order like the values).  `hist` has 2 x 256 words, used in turn so
+// The k-th smallest (0-based) of the values of m[0..cnt) in LDS that exceed
+// `above` (default: all), by most-significant-digit radix selection on the
+// bit patterns (the values are non-negative, so their patterns order like the
+// values).  `hist` has 2 x 256 words, used in turn so
 // that each pass clears the next pass's histogram while it counts; `sh` has 4
 // words (the chosen digit and rank, also in turn).
 template <typename R>
 __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
-                                                uint32_t *sh) {
+                                                uint32_t *sh, R above = (R)-1) {
   using K = typename CT<R>::K;
   constexpr int NB = sizeof(K) * 8;
   K prefix = 0, mask = 0;
@@ -223,8 +224,9 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
     uint32_t *hn = hist + 256 * ((pass + 1) & 1);
     uint32_t *out = sh + 2 * (pass & 1);
     for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
-      const K key = key_of(m[b]);
-      if ((key & mask) == prefix) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+      const R mb = m[b];
+      const K key = key_of(mb);
+      if ((key & mask) == prefix && (above < (R)0 || mb > above)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
     }
     if (shift > 0)
       for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hn[i] = 0;
@@ -584,7 +586,8 @@ template <typename R, int RB> __device__ __forceinline__ void dft_reg(typename C
   }
 }
 
-// One pass of the in-place decimation-in-time DFT on bit-reversed input: the
+// One pass of the in-place decimation-in-time DFT on bit-reversed input (count
+// a power of two): the
 // completed sub-transforms of length L = 2^logL are combined RAD = 2^RB at a
 // time into length RAD L.  For offset p < L the RAD inputs are taken from
 // sub-transforms in bit-reversed order (which is how the radix-2 stages this
@@ -599,8 +602,13 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
   const uint32_t total = count << gl;
   const uint32_t L = 1u << logL;
   const R inv_n2 = (R)1 / (R)(L << RB);
+  // transforms along a strided axis (2D columns) put neighbouring threads on
+  // neighbouring transforms, so that their LDS accesses are contiguous
+  const bool ffast = fstride < estride;
+  const uint32_t lc = ffast ? 31u - __clz(count) : 0u;
   for (uint32_t kk = threadIdx.x; kk < total; kk += blockDim.x) {
-    const uint32_t f = kk >> gl, q = kk & ((1u << gl) - 1u);
+    const uint32_t f = ffast ? (kk & (count - 1u)) : (kk >> gl);
+    const uint32_t q = ffast ? (kk >> lc) : (kk & ((1u << gl) - 1u));
     const uint32_t p = q & (L - 1u), g = q >> logL;
     C *base = buf + f * fstride + (((g << (logL + RB)) + p) * estride);
     const uint32_t step = L * estride;
@@ -958,49 +966,54 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
 
   // bucket DFT
   C *buf = reinterpret_cast<C *>(smem);
-  for (uint32_t b = tid; b < Bc; b += T) {
-    uint32_t dst;
-    if (NDIM == 1) {
-      dst = bitrev(b, logB);
-    } else {
-      dst = (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
-    }
-    // the slab partials of k_hash, added in slab order (in FP64 for the
-    // compensated FP32 fold)
-    C v = yg[b];
-    if (main_phase && P.rows2d == 1) {
-      // the row hash completed the bucket sums: nothing to add
-    } else if (main_phase && P.rows2d == 2) {
-      // the streamed row hash leaves one partial per row wrap; the slots
-      // past the last wrap are read (they lie in the array) but not used
-      const uint32_t nsl = min(P.alpha * B, P.n) >> logB;
-      C u[kSlabs];
+  auto dst_of = [&](uint32_t b) -> uint32_t {
+    if (NDIM == 1) return bitrev(b, logB);
+    return (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
+  };
+  // the partials are added in slab (or row-wrap) order: the streamed 2D row
+  // hash leaves one per row wrap (slots past the last wrap are read, they lie
+  // in the array, but not used), the row hash one in all, k_hash kSlabs; the
+  // compensated FP32 fold adds them in FP64.  kSumU buckets per thread have
+  // their loads issued together.
+  const uint32_t nsl = !main_phase ? (uint32_t)kSlabs
+                       : P.rows2d == 1 ? 1u
+                       : P.rows2d == 2 ? (min(P.alpha * B, P.n) >> logB)
+                                       : (uint32_t)kSlabs;
+  constexpr int kSumU = sizeof(R) == 4 ? 4 : 2;
+  for (uint32_t b0 = tid; b0 < Bc; b0 += kSumU * T) {
+    C u[kSumU][kSlabs];
 #pragma unroll
-      for (int sl = 1; sl < kSlabs; ++sl) u[sl] = yg[(size_t)sl * sstride + b];
+    for (int k = 0; k < kSumU; ++k) {
+      const uint32_t b = b0 + (uint32_t)k * T;
 #pragma unroll
-      for (int sl = 1; sl < kSlabs; ++sl) {
-        v.x += (uint32_t)sl < nsl ? u[sl].x : (R)0;
-        v.y += (uint32_t)sl < nsl ? u[sl].y : (R)0;
-      }
-    } else if (P.comp) {
-      double vx = v.x, vy = v.y;
-#pragma unroll
-      for (int sl = 1; sl < kSlabs; ++sl) {
-        const C u = yg[(size_t)sl * sstride + b];
-        vx += (double)u.x;
-        vy += (double)u.y;
-      }
-      v.x = (R)vx;
-      v.y = (R)vy;
-    } else {
-#pragma unroll
-      for (int sl = 1; sl < kSlabs; ++sl) {
-        const C u = yg[(size_t)sl * sstride + b];
-        v.x += u.x;
-        v.y += u.y;
+      for (int sl = 0; sl < kSlabs; ++sl) {
+        u[k][sl].x = 0;
+        u[k][sl].y = 0;
+        if (b < Bc && (sl == 0 || nsl > 1u)) u[k][sl] = yg[(size_t)sl * sstride + b];
       }
     }
-    buf[dst] = v;
+#pragma unroll
+    for (int k = 0; k < kSumU; ++k) {
+      const uint32_t b = b0 + (uint32_t)k * T;
+      C v = u[k][0];
+      if (P.comp && !(main_phase && P.rows2d)) {
+        double vx = v.x, vy = v.y;
+#pragma unroll
+        for (int sl = 1; sl < kSlabs; ++sl) {
+          vx += (double)u[k][sl].x;
+          vy += (double)u[k][sl].y;
+        }
+        v.x = (R)vx;
+        v.y = (R)vy;
+      } else {
+#pragma unroll
+        for (int sl = 1; sl < kSlabs; ++sl) {
+          v.x += (uint32_t)sl < nsl ? u[k][sl].x : (R)0;
+          v.y += (uint32_t)sl < nsl ? u[k][sl].y : (R)0;
+        }
+      }
+      if (b < Bc) buf[dst_of(b)] = v;
+    }
   }
   __syncthreads();
   if (NDIM == 1) {
@@ -1116,7 +1129,9 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
       mine += f;
     }
   } else {
-    const R v = block_kth_smallest<R>(ms, Bc, Bc - num, hist, sh);
+    // the num-th largest: among the n_above values above T, the
+    // (n_above - num)-th smallest
+    const R v = block_kth_smallest<R>(ms, Bc, n_above - num, hist, sh, Tr);
     uint32_t gt = 0, ties = 0;
     for (uint32_t j = 0; j < cnt; ++j) {
       const R mj = ms[start + j];
