@@ -214,7 +214,9 @@ Layout make_layout(const atsfft_plan_s *p, int32_t batch) {
   l.jlist_loop = align_up(Bc * 4, 16);
   l.jlist = off;
   off = align_up(off + (size_t)d.L_loc * l.jlist_loop, A);
-  l.S = off;
+  l.S = off;  // located set in vote order
+  off = align_up(off + (size_t)d.max_out * 4, A);
+  l.Ssort = off;  // the same, ascending (aligned with the tape)
   off = align_up(off + (size_t)d.max_out * 4, A);
   l.tape = off;  // median loops of each located frequency (adjoint)
   off = align_up(off + (size_t)d.max_out * 2, A);

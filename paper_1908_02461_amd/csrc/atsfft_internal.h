@@ -15,6 +15,8 @@ constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap grou
 constexpr int kSlabs = 8;            // address slabs of a signal, one per XCD
 constexpr int kVoteThreads = 256;
 constexpr int kEstThreads = 256;
+constexpr int kEstGroups = 4;          // estimate workgroups per signal
+constexpr uint32_t kEstRankMax = 1024; // located sets up to this size are sorted by rank
 constexpr int kGatherThreads = 256;  // adjoint gather: threads per block
 constexpr int kGatherPer = 4;        // addresses per thread and pass
 constexpr int kRowTaps = 8;                // 2D row hash: column wraps per thread, at most
@@ -62,7 +64,7 @@ static_assert(sizeof(ProbeRec) == 32, "ProbeRec layout");
 struct Layout {
   size_t slice;
   size_t state, hist, yprobe, ymain, ymain_loop, tloc, jcount;
-  size_t jbits, jbits_loop, jlist, jlist_loop, S, tape, bflag, resid;
+  size_t jbits, jbits_loop, jlist, jlist_loop, S, Ssort, tape, bflag, resid;
   size_t total;
 };
 

@@ -126,6 +126,9 @@ __device__ __forceinline__ int32_t *jlist_of(const KParams &P, uint32_t sig, uin
 __device__ __forceinline__ uint32_t *S_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.S);
 }
+__device__ __forceinline__ uint32_t *Ssort_of(const KParams &P, uint32_t sig) {
+  return reinterpret_cast<uint32_t *>(slice_of(P, sig) + P.lay.Ssort);
+}
 __device__ __forceinline__ double *resid_of(const KParams &P, uint32_t sig) {
   return reinterpret_cast<double *>(slice_of(P, sig) + P.lay.resid);
 }
@@ -1373,12 +1376,15 @@ template <typename R, int N> __device__ __forceinline__ void sort_net(R (&a)[N])
 
 // Sort S ascending, then for each located f and estimation loop l the
 // estimator display: e_l(f) = y_hat_l[h_l(f)] omega^{tau_l f} / G'(o_l(f)),
-// and the coordinate-wise median over the L_est loops.
+// and the coordinate-wise median over the L_est loops.  The kEstGroups
+// workgroups of a signal each sort S (by rank when |S| <= kEstRankMax: the
+// entries are distinct, so each lands at the count of smaller ones) and take
+// every kEstGroups-th block of kEstThreads located frequencies.
 template <typename R, int NDIM, int ML>
 __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t sig = blockIdx.x;
+  const uint32_t sig = blockIdx.y, grp = blockIdx.x;
   SigState *st = state_of(P, sig);
   const SigState s = *st;
   __syncthreads();
@@ -1387,7 +1393,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   const bool empty = (s.status & kSigEmpty) != 0;
   const uint32_t count = empty ? 0u : s.count;
   if (!empty && count > P.max_out) status |= kSigTruncated;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && grp == 0) {
     const int64_t slot = out_slot(P, sig);
     P.khat[slot] = s.khat;
     P.count[slot] = (int32_t)count;
@@ -1397,11 +1403,24 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   if (empty || count > P.max_out || count == 0) return;
 
   uint32_t *sS = reinterpret_cast<uint32_t *>(smem);
-  uint32_t P2 = 1;
-  while (P2 < count) P2 <<= 1;
   const uint32_t *S = S_of(P, sig);
-  for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) sS[i] = i < count ? S[i] : 0xFFFFFFFFu;
-  __syncthreads();
+  __shared__ uint32_t sIn[kEstRankMax];
+  uint32_t P2 = 1;
+  if (count <= kEstRankMax) {
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) sIn[i] = S[i];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+      const uint32_t v = sIn[i];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < count; ++j) r += sIn[j] < v ? 1u : 0u;
+      sS[r] = v;
+    }
+    __syncthreads();
+  } else {
+    while (P2 < count) P2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) sS[i] = i < count ? S[i] : 0xFFFFFFFFu;
+    __syncthreads();
+  }
   for (uint32_t k = 2; k <= P2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) {
@@ -1441,24 +1460,33 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   C *vals = reinterpret_cast<C *>(P.vals) + out_slot(P, sig) * P.max_out;
   const uint32_t Le = P.L_est;
 
-  uint32_t *Sg = S_of(P, sig);
+  // the sorted set goes to its own array: every workgroup reads S above
+  uint32_t *Sg = Ssort_of(P, sig);
   uint16_t *tape = tape_of(P, sig);
-  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+  for (uint32_t i = grp * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const uint32_t f = sS[i];
     R re[ML], im[ML], re0[ML], im0[ML];
+    // every loop's bucket value and window factor are loaded before any is
+    // used (slots past L_est repeat the last loop and are discarded)
+    EstTerm<R> t[ML];
+    C yv[ML];
+#pragma unroll
+    for (int l = 0; l < ML; ++l) {
+      const uint32_t lc = min((uint32_t)l, Le - 1u);
+      t[l] = est_term<R, NDIM>(es[lc], f, n, logn, logB, logW, c, gh);
+      yv[l] = ymain_of<C>(P, sig, P.L_loc + lc)[t[l].h];
+    }
 #pragma unroll
     for (int l = 0; l < ML; ++l) {
       re[l] = (R)INFINITY;
       im[l] = (R)INFINITY;
       if ((uint32_t)l < Le) {
-        const EstTerm<R> t = est_term<R, NDIM>(es[l], f, n, logn, logB, logW, c, gh);
-        const C yv = ymain_of<C>(P, sig, P.L_loc + l)[t.h];
         R sn, cs;
-        sincos_pi(-(R)t.phase * two_over_n, &sn, &cs);
-        const R zr = yv.x * cs - yv.y * sn;
-        const R zi = yv.x * sn + yv.y * cs;
-        re[l] = zr / t.g;
-        im[l] = zi / t.g;
+        sincos_pi(-(R)t[l].phase * two_over_n, &sn, &cs);
+        const R zr = yv[l].x * cs - yv[l].y * sn;
+        const R zi = yv[l].x * sn + yv[l].y * cs;
+        re[l] = zr / t[l].g;
+        im[l] = zi / t[l].g;
       }
       re0[l] = re[l];
       im0[l] = im[l];
@@ -1699,7 +1727,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bwd_bucket(KParams P, const 
     buf[b] = z;
   }
   __syncthreads();
-  const uint32_t *S = S_of(P, sig);
+  const uint32_t *S = Ssort_of(P, sig);
   const uint16_t *tape = tape_of(P, sig);
   const C *gv = reinterpret_cast<const C *>(grad_vals) + (int64_t)sig * P.max_out;
   for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
@@ -2055,11 +2083,11 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hipLaunchKernelGGL((k_vote<NDIM, false>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
     if (marks && mark) mark(ctx, 4);
     if (Q.L_est <= 8)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
     else if (Q.L_est <= 16)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
     else
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
   };
   main_pass(P, true);
   if (P.res_tol > 0.0) {
