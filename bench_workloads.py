@@ -139,15 +139,25 @@ def run_c4(args):
     total = int(ns.sum())
     _log(f"generating {batch} signals, {total * 8 / 2**30:.2f} GiB")
     x = torch.empty(total, dtype=torch.complex64, device="cuda")
-    planted = []
+    planted, truth = [], []
     for i in range(batch):
-        xi, locs, _ = synth.planted_1d_device(int(ns[i]), int(ks[i]), 3000 + i, mag=("uniform", 0.5, 1.0),
-                                              snr_db=float(snrs[i]))
+        xi, locs, amps = synth.planted_1d_device(int(ns[i]), int(ks[i]), 3000 + i, mag=("uniform", 0.5, 1.0),
+                                                 snr_db=float(snrs[i]))
         x[offs[i]:offs[i] + ns[i]] = xi
         planted.append(locs)
+        truth.append((locs, amps))
         if (i + 1) % 128 == 0:
             _log(f"  {i + 1}/{batch}")
-    plan = A.Plan(1, 1 << 22, "c64", seed=11, n_min=1 << 16, max_batch=batch)
+    # the knobs: the autotuner on this batch (filter factor and loop counts
+    # against recovery of the planted spectra), the library defaults as its
+    # baseline
+    from paper_1908_02461_amd import autotune
+
+    _log("autotuning")
+    tuned = autotune.tune_uneven(x, offs, ns, truth, n_max=1 << 22, n_min=1 << 16, seed=11)
+    knobs = tuned.knobs
+    _log(f"tuned knobs {knobs}")
+    plan = A.Plan(1, 1 << 22, "c64", seed=11, n_min=1 << 16, max_batch=batch, **knobs)
     out = plan.outputs(batch, x.device)
     step = lambda: plan.execute_uneven(x, offs, ns, out=out)
     o = step()
@@ -177,7 +187,7 @@ def run_c4(args):
         sat += bool(r["status"] & A.SIG_PROBE_SATURATED)
     # the plain per-signal form: every signal through a plan of its length,
     # one execute each; its traces give each signal's bucket count
-    plans = {m: A.Plan(1, m, "c64", seed=11, max_batch=1) for m in groups}
+    plans = {m: A.Plan(1, m, "c64", seed=11, max_batch=1, **knobs) for m in groups}
     pout = {m: p1.outputs(1, x.device) for m, p1 in plans.items()}
     pws = {m: p1.workspace(1, x.device) for m, p1 in plans.items()}
     views1 = [x[offs[i]:offs[i] + ns[i]].view(1, int(ns[i])) for i in range(batch)]
@@ -214,7 +224,11 @@ def run_c4(args):
     line.update({"dense_fft_ms_per_batch": ms_dense, "speedup_vs_dense_fft": ms_dense / ms,
                  "recovered_fraction": float(np.mean(rec)), "probe_saturated": sat,
                  "per_signal_ms_per_batch": ms_single, "batched_over_per_signal": ms_single / ms,
-                 "touched_bytes_per_batch": tb, "touched_gbs_per_batch_time": tb / (ms / 1e3) / 1e9})
+                 "touched_bytes_per_batch": tb, "touched_gbs_per_batch_time": tb / (ms / 1e3) / 1e9,
+                 "tuned_knobs": knobs, "default_knobs_ms_per_batch": tuned.baseline_ms_per_transform * batch,
+                 "tuning_candidates": [{"knobs": t["knobs"], "ms_per_batch": t["ms_per_transform"] * batch,
+                                        "recovery": t["recovery"], "l1_vs_planted": t["l1_vs_planted"]}
+                                       for t in tuned.tried if t["valid"]]})
     return line
 
 

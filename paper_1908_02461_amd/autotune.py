@@ -13,6 +13,11 @@ candidates within ``tie`` of the fastest are ranked by predicted touched bytes
 bucket count), so that a choice that measures the same but moves less memory
 is preferred.  Results are cached in a JSON file keyed by the class.
 
+An uneven batch (signals of several lengths in one call) is tuned on the call
+itself: ``tune_uneven`` times each candidate's execute_uneven on the caller's
+batch and scores it against the planted spectra the caller passes, with the
+same selection rule.
+
 Everything here drives the library through its Python binding; the method's
 arithmetic stays in the library.
 """
@@ -221,3 +226,69 @@ def tune(ndim: int, n: int, dtype: str = "c64", k_band: Sequence[int] = (4, 64),
     store[key] = asdict(out)
     save_cache(cache, store)
     return out
+
+
+def uneven_space() -> List[dict]:
+    """Candidates for an uneven 1D batch: filter factors 8, 16, 32 (a smaller
+    alpha also raises the bucket cap n / alpha of the short signals) and
+    (L, T) = (7, 4) or (9, 5)."""
+    return [dict(B0=32, alpha=a, L_loc=L, L_est=L, T_vote=T) for a in (8, 16, 32) for L, T in ((7, 4), (9, 5))]
+
+
+def measure_uneven(knobs: dict, x, offsets, ns, truth, n_max: int, n_min: int, dtype: str = "c64",
+                   seed: int = 0, steps: int = 3, warmup: int = 1) -> Measured:
+    """Time one candidate's execute_uneven on the packed batch x and score it
+    against the planted truth [(locs, amps)] of every signal."""
+    import torch
+
+    from . import atsfft as A
+
+    batch = len(ns)
+    try:
+        plan = A.Plan(1, n_max, dtype, seed=seed, n_min=n_min, max_batch=batch, **knobs)
+    except A.AtsfftError as e:
+        return Measured(dict(knobs), float("inf"), 0.0, float("inf"), valid=False, note=str(e))
+    out = plan.execute_uneven(x, offsets, ns)
+    ws = out["ws"]
+    for _ in range(warmup):
+        plan.execute_uneven(x, offsets, ns, out=out, ws=ws)
+    s = torch.cuda.current_stream(x.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        plan.execute_uneven(x, offsets, ns, out=out, ws=ws)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rec, err = [], []
+    for i in range(batch):
+        r = plan.results(out, i)
+        a, b = _planted_error(r["locs"], r["vals"], *truth[i])
+        rec.append(a)
+        err.append(b)
+    plan.close()
+    return Measured(dict(knobs), ms / batch, float(np.mean(rec)), float(np.mean(err)))
+
+
+def tune_uneven(x, offsets, ns, truth, n_max: int, n_min: int, dtype: str = "c64", seed: int = 0,
+                space: Optional[Iterable[dict]] = None, steps: int = 3, min_recovery: float = 0.99,
+                err_slack: float = 1.5, tie: float = 0.03) -> TuneResult:
+    """Pick the knobs for one uneven batch: the library defaults are the
+    baseline, every candidate of `space` (default uneven_space()) is measured
+    on the batch, and select() decides."""
+    from . import atsfft as A
+
+    d0 = A.default_desc(1, n_max, dtype)
+    base_knobs = {k: int(getattr(d0, k)) for k in KNOBS}
+    args = (x, offsets, ns, truth, n_max, n_min, dtype, seed, steps)
+    baseline = measure_uneven(base_knobs, *args)
+    results = [baseline]
+    for kn in (space if space is not None else uneven_space()):
+        if kn == base_knobs:
+            continue
+        results.append(measure_uneven(kn, *args))
+    best = select(results, baseline, min_recovery, err_slack, tie=tie)
+    key = f"1d-uneven/n{n_min}-{n_max}/{dtype}/b{len(ns)}"
+    return TuneResult(key=key, knobs=best.knobs, ms_per_transform=best.ms_per_transform, recovery=best.recovery,
+                      l1_vs_planted=best.l1_vs_planted, baseline_ms_per_transform=baseline.ms_per_transform,
+                      touched_bytes=best.touched_bytes, tried=[asdict(m) for m in results])
