@@ -213,3 +213,17 @@ def test_2d_main_hash_forms(A, monkeypatch, form, N, dt, knobs):
     for i in range(2):
         u, v = plan.results(out, i), plan.results(again, i)
         assert np.array_equal(u["locs"], v["locs"]) and np.array_equal(u["vals"], v["vals"])
+
+
+@pytest.mark.parametrize("k", [900, 1100])
+def test_large_located_sets(A, k):
+    """Located sets on either side of the estimator's 1024-entry rank sort
+    (above it the bitonic sort runs): Algorithm 1 form at B = 16384, n = 2^16,
+    alpha = 4, noiseless planted spectrum."""
+    n = 1 << 16
+    plan = A.Plan(1, n, "c64", seed=21, alpha=4, fixed_B=16384, fixed_k=k, max_batch=1)
+    x = synth.planted_1d(n, k, 400 + k, mag=("uniform", 0.5, 1.0), dtype=np.complex64)[0]
+    out, _ = _check_batch(A, plan, [x], f"large S k={k}")
+    res = plan.results(out, 0)
+    assert (res["count"] > 1024) == (k > 1024), res["count"]
+    assert np.all(np.diff(res["locs"]) > 0)
