@@ -596,7 +596,11 @@ template <typename R, int RB> __device__ __forceinline__ void dft_reg(typename C
 // sub-transforms in bit-reversed order (which is how the radix-2 stages this
 // pass replaces would have paired them), scaled by omega_{RAD L}^{j p}, and
 // transformed in registers; output m goes to position p + m L.
-template <typename R, int RB>
+// LDS index of element e when the buffer holds one pad element after every
+// 32 (PAD): strided passes and the bit-reversed load then spread over the banks
+template <bool PAD> __device__ __forceinline__ uint32_t lds_at(uint32_t e) { return PAD ? e + (e >> 5) : e; }
+
+template <typename R, int RB, bool PAD = false>
 __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, uint32_t logL, uint32_t count,
                                          uint32_t fstride, uint32_t estride) {
   using C = typename CT<R>::C;
@@ -613,13 +617,13 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
     const uint32_t f = ffast ? (kk & (count - 1u)) : (kk >> gl);
     const uint32_t q = ffast ? (kk >> lc) : (kk & ((1u << gl) - 1u));
     const uint32_t p = q & (L - 1u), g = q >> logL;
-    C *base = buf + f * fstride + (((g << (logL + RB)) + p) * estride);
+    const uint32_t base = f * fstride + (((g << (logL + RB)) + p) * estride);
     const uint32_t step = L * estride;
     C x[RAD];
 #pragma unroll
     for (int j = 0; j < RAD; ++j) {
       const int jr = RB == 1 ? j : RB == 2 ? ((j & 1) << 1 | (j >> 1)) : ((j & 1) << 2 | (j & 2) | (j >> 2));
-      x[j] = base[(uint32_t)jr * step];
+      x[j] = buf[lds_at<PAD>(base + (uint32_t)jr * step)];
     }
     if (logL > 0) {
       C w1;  // omega_{RAD L}^p, the angle an exact multiple of pi
@@ -633,7 +637,7 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
     }
     dft_reg<R, RB>(x);
 #pragma unroll
-    for (int m = 0; m < RAD; ++m) base[(uint32_t)m * step] = x[m];
+    for (int m = 0; m < RAD; ++m) buf[lds_at<PAD>(base + (uint32_t)m * step)] = x[m];
   }
   __syncthreads();
 }
@@ -643,19 +647,19 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
 // bit-reversed order; element j of transform f sits at
 // buf[f * fstride + j * estride].  Radix-8 passes, led by one radix-2 or
 // radix-4 pass when log2 B is not a multiple of 3.
-template <typename R>
+template <typename R, bool PAD = false>
 __device__ __forceinline__ void fft_axis(typename CT<R>::C *buf, uint32_t logB, uint32_t count, uint32_t fstride,
                                          uint32_t estride) {
   uint32_t logL = 0;
   const uint32_t lead = logB % 3;
   if (lead == 1) {
-    fft_pass<R, 1>(buf, logB, 0, count, fstride, estride);
+    fft_pass<R, 1, PAD>(buf, logB, 0, count, fstride, estride);
     logL = 1;
   } else if (lead == 2) {
-    fft_pass<R, 2>(buf, logB, 0, count, fstride, estride);
+    fft_pass<R, 2, PAD>(buf, logB, 0, count, fstride, estride);
     logL = 2;
   }
-  for (; logL < logB; logL += 3) fft_pass<R, 3>(buf, logB, logL, count, fstride, estride);
+  for (; logL < logB; logL += 3) fft_pass<R, 3, PAD>(buf, logB, logL, count, fstride, estride);
 }
 
 // key order of the local-maximum and cutoff steps: larger m first, equal m
@@ -1015,15 +1019,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
           v.y += (uint32_t)sl < nsl ? u[k][sl].y : (R)0;
         }
       }
-      if (b < Bc) buf[dst_of(b)] = v;
+      if (b < Bc) buf[lds_at<true>(dst_of(b))] = v;
     }
   }
   __syncthreads();
   if (NDIM == 1) {
-    fft_axis<R>(buf, logB, 1, 0, 1);
+    fft_axis<R, true>(buf, logB, 1, 0, 1);
   } else {
-    fft_axis<R>(buf, logB, B, B, 1);
-    fft_axis<R>(buf, logB, B, 1, B);
+    fft_axis<R, true>(buf, logB, B, B, 1);
+    fft_axis<R, true>(buf, logB, B, 1, B);
   }
   // y_hat back to the workspace; for probe and location loops also
   // m_b = |y_hat_b|^2 and the largest key, kept in registers while the DFT
@@ -1038,7 +1042,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     const uint32_t b = tid + (uint32_t)j * T;
     mv[j] = 0;
     if ((uint32_t)j < per && b < Bc) {
-      const C v = buf[b];
+      const C v = buf[lds_at<true>(b)];
       yg[b] = v;
       mv[j] = v.x * v.x + v.y * v.y;
       kmax = max(kmax, key_of(mv[j]));
@@ -1937,7 +1941,7 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
-  const size_t fft = 2 * rs * Bc_max;
+  const size_t fft = 2 * rs * (Bc_max + Bc_max / 32);  // one pad element per 32
   const size_t sel = ((rs * Bc_max + Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
