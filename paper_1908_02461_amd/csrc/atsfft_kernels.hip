@@ -295,6 +295,9 @@ __global__ void k_init(KParams P, int batch) {
     if (s.khat <= 0) s.status |= kSigEmpty;
   }
   *state_of(P, sig) = s;
+  // a probe level's count is -1 until its k_bucket workgroup stores it
+  ProbeRec *h = hist_of(P, sig);
+  for (uint32_t i = 0; i < P.probe_levels; ++i) h[i].k = -1;
 }
 
 // ------------------------------------------------------------- k_hash ----
@@ -887,14 +890,21 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
 template <int NDIM>
 __device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
   SigState *st = state_of(P, sig);
-  SigState s = *st;
+  SigState s = *st;  // written only by this routine and k_init, in earlier launches
   ProbeRec *hist = hist_of(P, sig);
   for (int i = lo; i < hi && !s.done; ++i) {
     ProbeRec *h = hist + i;
     const uint32_t B = (uint32_t)s.B;
     const uint32_t logB = ilog2(B);
     const long long Bc = NDIM == 1 ? (long long)B : (long long)B * B;
-    const int k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // every workgroup of the round stored its count before it counted itself
+    // in; a store still on its way reads as -1 (k_init's value) for a while
+    int k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int spin = 0; k < 0 && spin < (1 << 20); ++spin) {
+      __builtin_amdgcn_s_sleep(2);
+      k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (k < 0) k = 0;
     int dec = i == 0 ? 1 : brule(s.k_prev, k);
     if (P.gamma > 0 && Bc < (long long)P.gamma * (long long)k) dec = 1;
     s.visited |= 1u << logB;
@@ -938,7 +948,16 @@ __device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
       if (s.khat <= 0) s.status |= kSigEmpty;
     }
   }
-  *st = s;
+  // field by field: round_blocks, in the same line, is only ever updated
+  // atomically
+  st->B = s.B;
+  st->k_prev = s.k_prev;
+  st->done = s.done;
+  st->B_star = s.B_star;
+  st->khat = s.khat;
+  st->status = s.status;
+  st->visited = s.visited;
+  st->n_probe = s.n_probe;
 }
 
 // ------------------------------------------------------------ k_bucket ----
@@ -1083,23 +1102,27 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     // local maxima among significant buckets (1D ring / 2D torus neighbours)
     uint32_t c = 0;
     for (uint32_t b = tid; b < Bc; b += T) {
-      if (!(ms[b] > Tr)) continue;
-      bool is_max = true;
       if (NDIM == 1) {
-        is_max = key_gt(ms, b, (b - 1u) & (B - 1u)) && key_gt(ms, b, (b + 1u) & (B - 1u));
+        if (!(ms[b] > Tr)) continue;
+        c += key_gt(ms, b, (b - 1u) & (B - 1u)) && key_gt(ms, b, (b + 1u) & (B - 1u)) ? 1u : 0u;
       } else {
+        // all eight torus neighbours read and compared without branches
+        const R mb = ms[b];
         const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
-        for (int d1 = -1; d1 <= 1 && is_max; ++d1)
-          for (int d2 = -1; d2 <= 1; ++d2) {
-            if (d1 == 0 && d2 == 0) continue;
-            const uint32_t nb = (((b1 + d1) & (B - 1u)) << logB) | ((b2 + d2) & (B - 1u));
-            if (!key_gt(ms, b, nb)) {
-              is_max = false;
-              break;
-            }
+        const uint32_t rows[3] = {((b1 - 1u) & (B - 1u)) << logB, b1 << logB, ((b1 + 1u) & (B - 1u)) << logB};
+        const uint32_t cols[3] = {(b2 - 1u) & (B - 1u), b2, (b2 + 1u) & (B - 1u)};
+        bool is_max = mb > Tr;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            if (i == 1 && j == 1) continue;
+            const uint32_t nb = rows[i] | cols[j];
+            const R mn = ms[nb];
+            is_max = is_max & (mb > mn || (mb == mn && b < nb));
           }
+        c += is_max ? 1u : 0u;
       }
-      c += is_max ? 1u : 0u;
     }
     const uint32_t k = block_sum(c, &sh[4]);
     if (tid == 0) {
@@ -1108,8 +1131,10 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
       h->dec = 0;
       h->T = Td;
       __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // the last of the round's workgroups of this signal applies the rule
-      const uint32_t prior = __hip_atomic_fetch_add(&st->round_blocks, 1u, __ATOMIC_ACQ_REL,
+      // the last of the round's workgroups of this signal applies the rule;
+      // it reads only the counts, themselves atomics, so no fence (an
+      // agent-scope fence writes back and invalidates the L2)
+      const uint32_t prior = __hip_atomic_fetch_add(&st->round_blocks, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
       if (prior + 1u == gridDim.x) {
         __hip_atomic_store(&st->round_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
