@@ -234,10 +234,11 @@ def main():
     ap.add_argument("--no-per-signal", action="store_true", help="skip the plain per-signal form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5", "known_k"),
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5", "known_k", "ksweep"),
                     help="c2: 1D n=2^22 k=64 (default); c3: 2D 4096^2 k=256; c4: uneven batch of 512; "
                          "c5: forward + adjoint, batch 64 of n=2^20 k=128; "
-                         "known_k: ATSFFT against the known-k form of Algorithm 1")
+                         "known_k: ATSFFT against the known-k form of Algorithm 1; "
+                         "ksweep: n=2^22 for k = 16..256 against the dense FFT")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the transform of one signal does not span GPUs "

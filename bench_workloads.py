@@ -345,5 +345,56 @@ def run_known_k(args):
     return line
 
 
+def run_ksweep(args):
+    """The headline length (n = 2^22 c64, 40 dB, magnitudes uniform [0.5, 1])
+    across sparsities k = 16, 64, 128, 256: batched ATSFFT (library defaults,
+    16 signals per k) against the same GPU's dense FFT of the same batch."""
+    import torch
+
+    from paper_1908_02461_amd import atsfft as A
+    from paper_1908_02461_amd import synth
+
+    n, batch = 1 << 22, 16
+    rows = []
+    for k in (16, 64, 128, 256):
+        _log(f"k = {k}")
+        sig = [synth.planted_1d_device(n, k, 7000 + 100 * k + i, mag=("uniform", 0.5, 1.0), snr_db=40.0)
+               for i in range(batch)]
+        x = torch.stack([t[0] for t in sig]).contiguous()
+        plan = A.Plan(1, n, "c64", seed=5, max_batch=batch)
+        out = plan.outputs(batch, x.device)
+        ws = plan.workspace(batch, x.device)
+        step = lambda: plan.execute_batched(x, out=out, ws=ws)
+        for _ in range(args.warmup):
+            step()
+        ms = _timed(step, args.steps)
+        y = torch.empty_like(x)
+        dense = lambda: torch.fft.fft(x, dim=-1, out=y)
+        for _ in range(args.warmup):
+            dense()
+        ms_dense = _timed(dense, args.steps)
+        rec, err = [], []
+        for i in range(batch):
+            r = plan.results(out, i)
+            locs, amps = sig[i][1], sig[i][2]
+            hit = np.isin(locs, r["locs"])
+            rec.append(float(np.mean(hit)))
+            idx = np.searchsorted(r["locs"], locs[hit])
+            err.append(float(np.mean(np.abs(r["vals"][idx] - amps[hit]))) if hit.any() else float("nan"))
+        rows.append({"k": k, "ms_per_transform": ms / batch, "dense_fft_ms_per_transform": ms_dense / batch,
+                     "speedup_vs_dense_fft": ms_dense / ms, "recovered_fraction": float(np.mean(rec)),
+                     "mean_abs_err_recovered": float(np.nanmean(err)),
+                     "B_star": sorted({plan.trace(ws, i, full=False)["B_star"] for i in range(batch)})})
+        plan.close()
+        del x, y
+    worst = min(r["speedup_vs_dense_fft"] for r in rows)
+    line = _base("smallest speedup of batched ATSFFT over the same GPU's dense FFT, n=2^22, k in {16,64,128,256}",
+                 worst, "x", args, sum(r["ms_per_transform"] for r in rows) * batch,
+                 {"workload": "ksweep_1d_c64_n4m_snr40", "n": n, "k": [16, 64, 128, 256], "batch": batch})
+    line["per_k"] = rows
+    return line
+
+
 def run(args):
-    return {"c3": run_c3, "c4": run_c4, "c5": run_c5, "known_k": run_known_k}[args.workload](args)
+    return {"c3": run_c3, "c4": run_c4, "c5": run_c5, "known_k": run_known_k,
+            "ksweep": run_ksweep}[args.workload](args)
