@@ -351,9 +351,11 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
   using C = typename CT<R>::C;
   constexpr bool main_phase = MAIN;
   static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
-  const uint32_t slab = blockIdx.x % kSlabs;
-  const uint32_t slot = blockIdx.x / kSlabs;
-  const uint32_t nslots = gridDim.x / kSlabs;
+  // 2D probe levels read few rows more than once: one slab, no row filter
+  constexpr uint32_t NS = (MAIN || NDIM == 1) ? (uint32_t)kSlabs : 1u;
+  const uint32_t slab = blockIdx.x % NS;
+  const uint32_t slot = blockIdx.x / NS;
+  const uint32_t nslots = gridDim.x / NS;
   const uint32_t sig = blockIdx.z;
   const SigState st = *state_of(P, sig);  // one 64-byte read
   uint32_t B, alpha, nl = 1;
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
         for (uint32_t r1 = g; r1 < wraps; r1 += 4) {
           const uint32_t i1 = b1 + (r1 << logB);
           const uint32_t a1 = (d0[0].sigma * (i1 - half) + d0[0].tau) & mask;
-          if ((a1 >> slab_shift) != slab) continue;
+          if (NS > 1u && (a1 >> slab_shift) != slab) continue;
           const R g1 = G[i1];
           const C *row = x + (size_t)a1 * n;
           for (uint32_t r0 = 0; r0 < wraps; r0 += kHashU) {
@@ -1001,7 +1003,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   // in the array, but not used), the row hash one in all, k_hash kSlabs; the
   // compensated FP32 fold adds them in FP64.  kSumU buckets per thread have
   // their loads issued together.
-  const uint32_t nsl = !main_phase ? (uint32_t)kSlabs
+  const uint32_t nsl = !main_phase ? (NDIM == 1 ? (uint32_t)kSlabs : 1u)
                        : P.rows2d == 1 ? 1u
                        : P.rows2d == 2 ? (min(P.alpha * B, P.n) >> logB)
                                        : (uint32_t)kSlabs;
@@ -2053,12 +2055,13 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hi = min(hi, P.probe_levels);
       const uint32_t Bt = P.B0 << (hi - 1);
       const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
+      constexpr uint32_t kProbeSlabs = NDIM == 1 ? (uint32_t)kSlabs : 1u;
       const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
       if (sizeof(R) == 4 && P.comp)
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false>), dim3(kSlabs * slots, hi - lo, batch),
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false>), dim3(kProbeSlabs * slots, hi - lo, batch),
                            dim3(kHashThreads), 0, s, P, (int)lo);
       else
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false>), dim3(kSlabs * slots, hi - lo, batch),
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false>), dim3(kProbeSlabs * slots, hi - lo, batch),
                            dim3(kHashThreads), 0, s, P, (int)lo);
       hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       lo = hi;
