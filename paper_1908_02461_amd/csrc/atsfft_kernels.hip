@@ -226,11 +226,23 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
     uint32_t *h = hist + 256 * (pass & 1);
     uint32_t *hn = hist + 256 * ((pass + 1) & 1);
     uint32_t *out = sh + 2 * (pass & 1);
+    // a thread adds runs of equal digits in one atomic: the leading digits
+    // are shared by most values, and same-address atomics serialise
+    uint32_t run_bin = 0, run = 0;
     for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
       const R mb = m[b];
       const K key = key_of(mb);
-      if ((key & mask) == prefix && (above < (R)0 || mb > above)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+      if ((key & mask) == prefix && (above < (R)0 || mb > above)) {
+        const uint32_t bin = (uint32_t)(key >> shift) & 255u;
+        if (run && bin != run_bin) {
+          atomicAdd(&h[run_bin], run);
+          run = 0;
+        }
+        run_bin = bin;
+        ++run;
+      }
     }
+    if (run) atomicAdd(&h[run_bin], run);
     if (shift > 0)
       for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hn[i] = 0;
     __syncthreads();
