@@ -788,6 +788,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_rows(KParams P) {
 // written by exactly one row and k_bucket adds a bucket's partials in r1
 // order, so the result does not depend on scheduling.  Needs w / B <= 8
 // partials and B <= the workgroup size.
+// rows are read once: non-temporal loads, so that they do not push the
+// partials (read back by k_bucket) out of the caches
+typedef float nt4 __attribute__((ext_vector_type(4)));
 template <typename R, int U>
 __global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
   using C = typename CT<R>::C;
@@ -837,7 +840,11 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
     const float4 *src_ = xs + (size_t)(A1) * units;                  \
     _Pragma("unroll") for (int k = 0; k < U; ++k) {                  \
       const uint32_t q = tid + (uint32_t)k * T;                      \
-      pf[k] = q < units ? src_[q] : make_float4(0.f, 0.f, 0.f, 0.f); \
+      pf[k] = make_float4(0.f, 0.f, 0.f, 0.f);                       \
+      if (q < units) {                                               \
+        const nt4 t_ = __builtin_nontemporal_load(reinterpret_cast<const nt4 *>(src_) + q); \
+        pf[k] = make_float4(t_.x, t_.y, t_.z, t_.w);                 \
+      }                                                              \
     }                                                                \
   }
   const uint32_t nrows = P.stream_rows, a_lo = blockIdx.x * nrows;
