@@ -180,6 +180,18 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  * flat window of Sec. II-A-2 generated in FP64, stored in the plan's
  * precision) and keeps them until atsfft_destroy.  On error *out is NULL.
  * Errors: ATSFFT_EINVAL, ATSFFT_ENODEVICE, ATSFFT_ENOMEM, ATSFFT_ELAUNCH.
+ *
+ * Launch-shape settings, read from the environment when a plan is created
+ * (for measurement; the defaults are the measured best on gfx950, and none of
+ * them changes a result beyond the order of floating-point sums):
+ *   ATSFFT_HASH_LOOPS    1D main loops per hash workgroup, 1..3 (1)
+ *   ATSFFT_TILE_SLOTS    hash workgroups per slab and loop, 1..64 (32)
+ *   ATSFFT_VOTE_BLOCKS   vote workgroups per candidate loop (128 / batch, >= 32)
+ *   ATSFFT_PROBE_FIRST   the first probe launch covers B up to this (2048)
+ *   ATSFFT_PROBE_STEP    probe levels per later launch, 1..32 (2)
+ *   ATSFFT_ROWS2D        2D main-loop hash: 0 slab gather, 1 per bucket row,
+ *                        2 rows streamed once; only lowers the plan's form (2)
+ *   ATSFFT_STREAM_ROWS   rows per workgroup of the streamed 2D hash, 1..64 (2)
  */
 atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d);
 
