@@ -204,7 +204,8 @@ def run_c4(args):
         m = int(ns[i])
         plans[m].execute_batched(views1[i], out=pout[m], ws=pws[m])
         Bs.append(plans[m].trace(pws[m], 0, full=False)["B_star"])
-    # touched bytes of the main loops (SURVEY d-2), each signal at the B of
+    # touched bytes of the main loops (distinct 128-byte input lines plus the
+    # bucket values written), each signal at the B of
     # its per-signal run and with the draws of its index in the uneven call
     import bench
 

@@ -105,7 +105,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1908_02461_amd.build")
     L = C.CDLL(LIB_PATH)
     vp, sz = C.c_void_p, C.c_size_t
     L.atsfft_default_desc.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int64, C.c_int32]
