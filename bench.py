@@ -211,6 +211,27 @@ def cpu_baseline_uneven(budget_s, workers=None):
                       f"{workers} processes, {el:.1f} s wall"}
 
 
+def copy_bandwidth_gbs(reps: int = 10) -> float:
+    """Attainable HBM bandwidth: a plain 1 GiB device-to-device copy (1 GiB
+    read + 1 GiB written), timed with HIP events."""
+    import torch
+
+    src = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
 def copy_calibration():
     """One plain 1 GiB device copy: the reference for the HBM byte counters."""
     import torch
@@ -325,6 +346,7 @@ def main():
     achieved = alg_bytes / hash_s / 1e9
     log("touched lines")
     touched_main, touched_step = touched_bytes(d, trs)
+    copy_gbs = copy_bandwidth_gbs()
 
     # plain per-signal form
     plan1 = A.Plan(1, n, "c64", seed=PLAN_SEED, max_batch=1)
@@ -409,7 +431,8 @@ def main():
                      "kernel": "k_hash (main loops)", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": stage_ms["hash_main"],
                      "touched_bytes_per_launch": touched_main,
-                     "touched_frac": touched_main / hash_s / 1e9 / HBM_PEAK_GBS},
+                     "touched_frac": touched_main / hash_s / 1e9 / HBM_PEAK_GBS,
+                     "attainable_copy_gbs": copy_gbs},
         "touched_bytes_per_step": touched_step,
         "touched_frac_of_step": touched_step / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "cpu_baseline": cpu,

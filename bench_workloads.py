@@ -83,14 +83,14 @@ def run_c3(args):
     stages = {kk: v / pr["executes"] for kk, v in pr.items() if kk != "executes"}
     alg = hash2d_stream_bytes(prof.desc, [prof.trace(pws, i, full=False) for i in range(batch)])
     hms = stages["hash_main"]
-    from bench import ROOT, measured_traffic, section_sha256
+    from bench import ROOT, copy_bandwidth_gbs, measured_traffic, section_sha256
 
     traffic = measured_traffic(batch, os.path.join(ROOT, "profiles", "hash2d_stream_c3_n4096_k256_b8_hbm_traffic.txt"),
                                section_sha256("2D row hash", "probe control"), key="section_sha256")
     line["roofline"] = {"bound": "hbm", "achieved": alg / (hms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
                         "frac": alg / (hms * 1e-3) / 8e12, "traffic": traffic,
                         "kernel": "k_hash2d_stream (main loops)", "alg_bytes_per_launch": alg,
-                        "avg_launch_ms": hms}
+                        "avg_launch_ms": hms, "attainable_copy_gbs": copy_bandwidth_gbs()}
     line["stage_ms_per_step"] = stages
     prof.close()
     return line
