@@ -230,9 +230,10 @@ def tune(ndim: int, n: int, dtype: str = "c64", k_band: Sequence[int] = (4, 64),
 
 def uneven_space() -> List[dict]:
     """Candidates for an uneven 1D batch: filter factors 8, 16, 32 (a smaller
-    alpha also raises the bucket cap n / alpha of the short signals) and
-    (L, T) = (7, 4) or (9, 5)."""
-    return [dict(B0=32, alpha=a, L_loc=L, L_est=L, T_vote=T) for a in (8, 16, 32) for L, T in ((7, 4), (9, 5))]
+    alpha also raises the bucket cap n / alpha of the short signals), (L, T) =
+    (7, 4) or (9, 5), and probe filter factors 8 or 16."""
+    return [dict(B0=32, alpha=a, L_loc=L, L_est=L, T_vote=T, alpha_probe=ap)
+            for a in (8, 16, 32) for L, T in ((7, 4), (9, 5)) for ap in (8, 16)]
 
 
 def measure_uneven(knobs: dict, x, offsets, ns, truth, n_max: int, n_min: int, dtype: str = "c64",
@@ -279,7 +280,7 @@ def tune_uneven(x, offsets, ns, truth, n_max: int, n_min: int, dtype: str = "c64
     from . import atsfft as A
 
     d0 = A.default_desc(1, n_max, dtype)
-    base_knobs = {k: int(getattr(d0, k)) for k in KNOBS}
+    base_knobs = {k: int(getattr(d0, k)) for k in KNOBS + ("alpha_probe",)}
     args = (x, offsets, ns, truth, n_max, n_min, dtype, seed, steps)
     baseline = measure_uneven(base_knobs, *args)
     results = [baseline]
