@@ -1122,27 +1122,44 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   if (!main_phase) {
     // local maxima among significant buckets (1D ring / 2D torus neighbours)
     uint32_t c = 0;
-    for (uint32_t b = tid; b < Bc; b += T) {
-      if (NDIM == 1) {
+    if (NDIM == 1) {
+      for (uint32_t b = tid; b < Bc; b += T) {
         if (!(ms[b] > Tr)) continue;
         c += key_gt(ms, b, (b - 1u) & (B - 1u)) && key_gt(ms, b, (b + 1u) & (B - 1u)) ? 1u : 0u;
-      } else {
-        // all eight torus neighbours read and compared without branches
-        const R mb = ms[b];
-        const uint32_t b1 = b >> logB, b2 = b & (B - 1u);
-        const uint32_t rows[3] = {((b1 - 1u) & (B - 1u)) << logB, b1 << logB, ((b1 + 1u) & (B - 1u)) << logB};
-        const uint32_t cols[3] = {(b2 - 1u) & (B - 1u), b2, (b2 + 1u) & (B - 1u)};
-        bool is_max = mb > Tr;
+      }
+    } else {
+      // four buckets of a row per step: the three rows' six columns around
+      // them (wrapping on the torus) are read once and every bucket is
+      // compared with its eight neighbours without branches (B >= 4)
+      for (uint32_t b0 = 4u * tid; b0 < Bc; b0 += 4u * T) {
+        const uint32_t b1 = b0 >> logB, c0 = b0 & (B - 1u);
+        uint32_t ridx[3];
+        R v[3][6];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i) {
+          ridx[i] = ((b1 + (uint32_t)i - 1u) & (B - 1u)) << logB;
+          const R *rowp = ms + ridx[i];
+          v[i][0] = rowp[(c0 - 1u) & (B - 1u)];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            if (i == 1 && j == 1) continue;
-            const uint32_t nb = rows[i] | cols[j];
-            const R mn = ms[nb];
-            is_max = is_max & (mb > mn || (mb == mn && b < nb));
-          }
-        c += is_max ? 1u : 0u;
+          for (int j = 0; j < 4; ++j) v[i][1 + j] = rowp[c0 + (uint32_t)j];
+          v[i][5] = rowp[(c0 + 4u) & (B - 1u)];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const R mb = v[1][1 + j];
+          const uint32_t b = ridx[1] | (c0 + (uint32_t)j);
+          bool is_max = mb > Tr;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+              if (i == 1 && dj == 0) continue;
+              const R mn = v[i][1 + j + dj];
+              const uint32_t nb = ridx[i] | ((c0 + (uint32_t)(j + dj)) & (B - 1u));
+              is_max = is_max & (mb > mn || (mb == mn && b < nb));
+            }
+          c += is_max ? 1u : 0u;
+        }
       }
     }
     const uint32_t k = block_sum(c, &sh[4]);
