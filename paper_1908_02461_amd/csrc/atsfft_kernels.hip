@@ -574,9 +574,54 @@ template <typename C> __device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, 
   x3 = csub(a1, a3);
 }
 
+// 16-point DFT, natural order in and out, as 4 x 4: DFTs of the four
+// stride-4 subsequences, twiddles omega_16^{n2 k1}, DFTs across them
+template <typename R> __device__ __forceinline__ void dft16(typename CT<R>::C *x) {
+  using C = typename CT<R>::C;
+  const R c1 = (R)0.92387953251128675612818318939678828;  // cos(pi / 8)
+  const R s1 = (R)0.38268343236508977172845998403039887;  // sin(pi / 8)
+  const R h = (R)0.70710678118654752440084436210484904;   // cos(pi / 4)
+  C y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = x[n2];
+    y[n2][1] = x[4 + n2];
+    y[n2][2] = x[8 + n2];
+    y[n2][3] = x[12 + n2];
+    dft4(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
+  }
+  auto tw = [](C a, R wr, R wi) {
+    C r;
+    r.x = a.x * wr - a.y * wi;
+    r.y = a.x * wi + a.y * wr;
+    return r;
+  };
+  // omega_16^m = cos(2 pi m / 16) - i sin(2 pi m / 16) for m = n2 k1
+  y[1][1] = tw(y[1][1], c1, -s1);  // m = 1
+  y[1][2] = tw(y[1][2], h, -h);    // m = 2
+  y[1][3] = tw(y[1][3], s1, -c1);  // m = 3
+  y[2][1] = tw(y[2][1], h, -h);    // m = 2
+  y[2][2] = mul_mi(y[2][2]);       // m = 4
+  y[2][3] = tw(y[2][3], -h, -h);   // m = 6
+  y[3][1] = tw(y[3][1], s1, -c1);  // m = 3
+  y[3][2] = tw(y[3][2], -h, -h);   // m = 6
+  y[3][3] = tw(y[3][3], -c1, s1);  // m = 9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+    dft4(a0, a1, a2, a3);
+    x[k1] = a0;
+    x[k1 + 4] = a1;
+    x[k1 + 8] = a2;
+    x[k1 + 12] = a3;
+  }
+}
+
 template <typename R, int RB> __device__ __forceinline__ void dft_reg(typename CT<R>::C *x) {
   using C = typename CT<R>::C;
-  if (RB == 1) {
+  if (RB == 4) {
+    dft16<R>(x);
+  } else if (RB == 1) {
     const C a = x[0];
     x[0] = cadd(a, x[1]);
     x[1] = csub(a, x[1]);
@@ -639,7 +684,10 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
     C x[RAD];
 #pragma unroll
     for (int j = 0; j < RAD; ++j) {
-      const int jr = RB == 1 ? j : RB == 2 ? ((j & 1) << 1 | (j >> 1)) : ((j & 1) << 2 | (j & 2) | (j >> 2));
+      const int jr = RB == 1   ? j
+                     : RB == 2 ? ((j & 1) << 1 | (j >> 1))
+                     : RB == 3 ? ((j & 1) << 2 | (j & 2) | (j >> 2))
+                               : ((j & 1) << 3 | (j & 2) << 1 | (j & 4) >> 1 | (j >> 3));
       x[j] = buf[lds_at<PAD>(base + (uint32_t)jr * step)];
     }
     if (logL > 0) {
@@ -664,10 +712,24 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
 // bit-reversed order; element j of transform f sits at
 // buf[f * fstride + j * estride].  Radix-8 passes, led by one radix-2 or
 // radix-4 pass when log2 B is not a multiple of 3.
-template <typename R, bool PAD = false>
+template <typename R, bool PAD = false, bool R16 = false>
 __device__ __forceinline__ void fft_axis(typename CT<R>::C *buf, uint32_t logB, uint32_t count, uint32_t fstride,
                                          uint32_t estride) {
   uint32_t logL = 0;
+  if (R16) {
+    // radix-16 passes led by one radix-2, -4 or -8 pass (for arrays with
+    // enough groups per pass to occupy the workgroup)
+    const uint32_t lead = logB % 4;
+    if (lead == 1) {
+      fft_pass<R, 1, PAD>(buf, logB, 0, count, fstride, estride);
+    } else if (lead == 2) {
+      fft_pass<R, 2, PAD>(buf, logB, 0, count, fstride, estride);
+    } else if (lead == 3) {
+      fft_pass<R, 3, PAD>(buf, logB, 0, count, fstride, estride);
+    }
+    for (logL = lead; logL < logB; logL += 4) fft_pass<R, 4, PAD>(buf, logB, logL, count, fstride, estride);
+    return;
+  }
   const uint32_t lead = logB % 3;
   if (lead == 1) {
     fft_pass<R, 1, PAD>(buf, logB, 0, count, fstride, estride);
@@ -1066,8 +1128,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   if (NDIM == 1) {
     fft_axis<R, true>(buf, logB, 1, 0, 1);
   } else {
-    fft_axis<R, true>(buf, logB, B, B, 1);
-    fft_axis<R, true>(buf, logB, B, 1, B);
+    fft_axis<R, true, true>(buf, logB, B, B, 1);
+    fft_axis<R, true, true>(buf, logB, B, 1, B);
   }
   // y_hat back to the workspace; for probe and location loops also
   // m_b = |y_hat_b|^2 and the largest key, kept in registers while the DFT
