@@ -693,11 +693,32 @@ __device__ __forceinline__ void fft_pass(typename CT<R>::C *buf, uint32_t logB, 
     if (logL > 0) {
       C w1;  // omega_{RAD L}^p, the angle an exact multiple of pi
       sincos_pi((R)(-2) * (R)p * inv_n2, &w1.y, &w1.x);
-      C wj = w1;
+      if (RB == 4) {
+        // omega^{jp} from omega^p, omega^{2p}, omega^{4p}, omega^{8p}: at
+        // most three products per twiddle instead of up to fifteen
+        C w[4];
+        w[0] = w1;
 #pragma unroll
-      for (int j = 1; j < RAD; ++j) {
-        x[j] = cmul(x[j], wj);
-        if (j + 1 < RAD) wj = cmul(wj, w1);
+        for (int e = 1; e < 4; ++e) sincos_pi((R)(-2) * (R)(p << e) * inv_n2, &w[e].y, &w[e].x);
+#pragma unroll
+        for (int j = 1; j < RAD; ++j) {
+          C wj;
+          bool first = true;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j & (1 << e)) {
+              wj = first ? w[e] : cmul(wj, w[e]);
+              first = false;
+            }
+          x[j] = cmul(x[j], wj);
+        }
+      } else {
+        C wj = w1;
+#pragma unroll
+        for (int j = 1; j < RAD; ++j) {
+          x[j] = cmul(x[j], wj);
+          if (j + 1 < RAD) wj = cmul(wj, w1);
+        }
       }
     }
     dft_reg<R, RB>(x);
