@@ -1147,7 +1147,11 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   }
   __syncthreads();
   if (NDIM == 1) {
-    fft_axis<R, true>(buf, logB, 1, 0, 1);
+    // radix-16 passes once a pass has groups for half the workgroup
+    if (logB >= 13)
+      fft_axis<R, true, true>(buf, logB, 1, 0, 1);
+    else
+      fft_axis<R, true>(buf, logB, 1, 0, 1);
   } else {
     fft_axis<R, true, true>(buf, logB, B, B, 1);
     fft_axis<R, true, true>(buf, logB, B, 1, B);
