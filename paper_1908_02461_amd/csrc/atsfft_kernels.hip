@@ -335,6 +335,7 @@ __global__ void k_init(KParams P, int batch) {
 // slab's partial y_b.  k_bucket adds the kSlabs partials in slab order.
 constexpr int kTile = 64;        // buckets per tile
 constexpr int kVoteIlp = 4;      // vote candidates tested together
+constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x column preimages
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
@@ -1349,26 +1350,35 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
 // L_loc - T_vote + 1 tests, so those run for every candidate without
 // branches, kVoteIlp candidates per thread; the few candidates still alive
 // then go through an LDS queue, so that the remaining tests, which stop at
-// the first hopeless miss, run only on them.  SMALL: every hash product fits
+// the first hopeless miss, run only on them.  In 2D a loop's bucket of (f1, f2)
+// is the pair of its bucket of f1 along rows and of f2 along columns, so a
+// thread tests a block of row x column preimages with one axis hash per row
+// and per column instead of two per pair.  SMALL: every hash product fits
 // 24-bit operands (1D n <= 2^24, and 2D), so the full-rate 24-bit multiply
 // gives the product modulo n.
 template <int NDIM, bool SMALL>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
   constexpr int K = kVoteIlp;
-  __shared__ uint32_t s_qf[kVoteThreads * K];
-  __shared__ uint8_t s_qv[kVoteThreads * K];
+  constexpr uint32_t KB = kVoteBlock2d;
+  // survivors of one round of first tests: K per thread, 2D KB x KB
+  constexpr uint32_t QCAP = kVoteThreads * (NDIM == 2 ? KB * KB : (uint32_t)K);
+  __shared__ uint32_t s_qf[QCAP];
+  __shared__ uint8_t s_qv[QCAP];
   __shared__ uint32_t s_qn;
   const uint32_t e = blockIdx.y, sig = blockIdx.z;
   SigState *st = state_of(P, sig);
   if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
   const int it0 = kPassIter * st->pass;
   const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
-  if (blockIdx.x >= ncand) return;
   const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
   const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
+  // workgroup work items: selected buckets, or in 2D rounds of KB x KB blocks
+  const bool blocks2 = NDIM == 2 && logW >= 2u;
+  const uint32_t items = blocks2 ? ((ncand << (2u * (logW - 2u))) + blockDim.x - 1u) / blockDim.x : ncand;
+  if (blockIdx.x >= items) return;
   const uint32_t L = P.L_loc, Tv = P.T_vote;
   const uint32_t words = (Bc + 31) >> 5;
   // tests before a candidate can fail; the slack of misses it may take
@@ -1410,6 +1420,121 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   };
 
   const uint32_t T = blockDim.x;
+  // a candidate after its first nA tests: emitted, queued for the rest of its
+  // tests, or dropped
+  auto keep = [&](uint32_t f, uint32_t v) {
+    if (v + slack >= nA && v < 0x80000000u) {
+      if (nA == L - 1u) {
+        if (1u + v >= Tv) emit(f);
+      } else {
+        const uint32_t q = atomicAdd(&s_qn, 1u);
+        s_qf[q] = f;
+        s_qv[q] = (uint8_t)v;
+      }
+    }
+  };
+  // the queued candidates' remaining tests, which stop at the first hopeless
+  // miss; every thread of the block calls this the same number of times
+  auto drain = [&]() {
+    __syncthreads();
+    const uint32_t qn = s_qn;
+    for (uint32_t q = threadIdx.x; q < qn; q += T) {
+      const uint32_t fq = s_qf[q];
+      uint32_t vq = s_qv[q];
+      uint32_t m = nA;
+      for (; m < L - 1u && vq + slack >= m; ++m) vq += in_J(other(m), bucket(other(m), fq));
+      if (vq + slack >= m && 1u + vq >= Tv) emit(fq);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_qn = 0;
+    // the next round's pushes come after this barrier
+    __syncthreads();
+  };
+
+  if (blocks2) {
+    // The W x W preimages of a selected bucket (b1, b2) are the pairs of its W
+    // row preimages f1 and W column preimages f2, and a loop hashes (f1, f2)
+    // to the pair of its axis buckets.  A thread takes a KB x KB block of one
+    // bucket's preimages: per loop it hashes KB row and KB column values and
+    // makes KB^2 bitmap tests.  The block's threads cover consecutive blocks
+    // of the selected buckets in list order.
+    const uint32_t lq = logW - 2u;  // block index bits per axis
+    const uint32_t logQ = 2u * lq;
+    const uint32_t units = ncand << logQ;
+    for (uint32_t u0 = blockIdx.x * T; u0 < units; u0 += gridDim.x * T) {
+      const uint32_t u = u0 + threadIdx.x;
+      const bool real = u < units;
+      const uint32_t j = (uint32_t)jl[real ? (u >> logQ) : 0u];
+      const uint32_t qi = u & ((1u << logQ) - 1u);
+      const uint32_t p1 = ((j >> logB) << logW) - c + ((qi >> lq) << 2);
+      const uint32_t p2 = ((j & (B - 1u)) << logW) - c + ((qi & ((1u << lq) - 1u)) << 2);
+      uint32_t f1[KB], f2[KB], v[KB * KB];
+#pragma unroll
+      for (uint32_t a = 0; a < KB; ++a) {
+        f1[a] = mulmod(inv0, (p1 + a) & mask);
+        f2[a] = mulmod(inv1, (p2 + a) & mask);
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < KB * KB; ++k) v[k] = real ? 0u : 0x80000000u;
+      // axis bucket: the product modulo 2^32, then modulo n
+      auto axis = [&](uint32_t sg, uint32_t f) -> uint32_t {
+        return (((SMALL ? __umul24(sg, f) : sg * f) + c) & mask) >> logW;
+      };
+      if (logB >= 5u) {
+        // a bitmap row is whole words: byte offsets of row h1's words and of
+        // h2's word within a row, and h2's bit
+        const char *bits = reinterpret_cast<const char *>(s_bits);
+        for (uint32_t m = 0; m < nA; ++m) {
+          const uint32_t l = other(m);
+          const uint32_t s1 = s_sig[l][0], s2 = s_sig[l][1];
+          uint32_t r[KB], w2[KB], t2[KB];
+#pragma unroll
+          for (uint32_t a = 0; a < KB; ++a) {
+            r[a] = (l * words + (axis(s1, f1[a]) << (logB - 5u))) << 2;
+            const uint32_t h2 = axis(s2, f2[a]);
+            w2[a] = (h2 >> 5) << 2;
+            t2[a] = h2 & 31u;
+          }
+#pragma unroll
+          for (uint32_t a = 0; a < KB; ++a) {
+#pragma unroll
+            for (uint32_t bb = 0; bb < KB; ++bb) {
+              const uint32_t word = *reinterpret_cast<const uint32_t *>(bits + r[a] + w2[bb]);
+              v[a * KB + bb] += (word >> t2[bb]) & 1u;
+            }
+          }
+        }
+      } else {
+        for (uint32_t m = 0; m < nA; ++m) {
+          const uint32_t l = other(m);
+          const uint32_t s1 = s_sig[l][0], s2 = s_sig[l][1];
+          // bit offsets: loop l's bitmap, then row h1 of it
+          uint32_t r[KB], h2[KB];
+#pragma unroll
+          for (uint32_t a = 0; a < KB; ++a) {
+            r[a] = ((l * words) << 5) + (axis(s1, f1[a]) << logB);
+            h2[a] = axis(s2, f2[a]);
+          }
+#pragma unroll
+          for (uint32_t a = 0; a < KB; ++a) {
+#pragma unroll
+            for (uint32_t bb = 0; bb < KB; ++bb) {
+              const uint32_t hb = r[a] + h2[bb];
+              v[a * KB + bb] += (s_bits[hb >> 5] >> (hb & 31u)) & 1u;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (uint32_t a = 0; a < KB; ++a) {
+#pragma unroll
+        for (uint32_t bb = 0; bb < KB; ++bb) keep((f1[a] << logn) | f2[bb], v[a * KB + bb]);
+      }
+      drain();
+    }
+    return;
+  }
+
   const uint32_t per = NDIM == 1 ? W : W * W;  // candidates per selected bucket
   for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
     const uint32_t j = (uint32_t)jl[jj];
@@ -1438,32 +1563,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] += in_J(l, h[k]);
       }
-      // alive: v >= nA - slack (and a real candidate)
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (v[k] + slack >= nA && v[k] < 0x80000000u) {
-          if (nA == L - 1u) {
-            if (1u + v[k] >= Tv) emit(f[k]);
-          } else {
-            const uint32_t q = atomicAdd(&s_qn, 1u);
-            s_qf[q] = f[k];
-            s_qv[q] = (uint8_t)v[k];
-          }
-        }
-      }
-      __syncthreads();
-      const uint32_t qn = s_qn;
-      for (uint32_t q = threadIdx.x; q < qn; q += T) {
-        const uint32_t fq = s_qf[q];
-        uint32_t vq = s_qv[q];
-        uint32_t m = nA;
-        for (; m < L - 1u && vq + slack >= m; ++m) vq += in_J(other(m), bucket(other(m), fq));
-        if (vq + slack >= m && 1u + vq >= Tv) emit(fq);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) s_qn = 0;
-      // the next block's pushes come after this barrier
-      __syncthreads();
+      for (int k = 0; k < K; ++k) keep(f[k], v[k]);
+      drain();
     }
   }
 }

@@ -227,3 +227,21 @@ def test_large_located_sets(A, k):
     res = plan.results(out, 0)
     assert (res["count"] > 1024) == (k > 1024), res["count"]
     assert np.all(np.diff(res["locs"]) > 0)
+
+
+@pytest.mark.parametrize("N,B,alpha,k", [
+    (64, 32, 2, 3),       # W = 2 preimages per axis: one candidate per thread
+    (128, 32, 4, 4),      # W = 4: one 4 x 4 block per bucket, word-aligned rows
+    (256, 16, 4, 5),      # rows of 16 bits: two rows per bitmap word
+    (1024, 8, 8, 4),      # W = 128: a bucket's blocks span four workgroup rounds
+    (128, 16, 8, 40),     # dense cutoffs: most candidates reach the queue
+])
+def test_2d_vote_blocks(A, N, B, alpha, k):
+    """The 2D vote's row x column blocks of preimages (and the per-candidate
+    form below four preimages per axis) give the oracle's located set, at
+    fixed B = B per axis with k given."""
+    plan = A.Plan(2, N, "c128", seed=31, max_batch=2, alpha=alpha, fixed_B=B, fixed_k=k)
+    xs = [synth.planted_2d(N, k, 90 + s, mag=("uniform", 0.5, 1.0))[0] for s in range(2)]
+    out, _ = _check_batch(A, plan, xs, f"2d vote N={N} B={B} alpha={alpha} k={k}")
+    for i in range(2):
+        assert plan.results(out, i)["count"] > 0
