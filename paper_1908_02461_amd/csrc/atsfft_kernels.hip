@@ -1400,14 +1400,19 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
   uint32_t *S = S_of(P, sig);
 
   auto mulmod = [&](uint32_t a, uint32_t b) -> uint32_t { return (SMALL ? __umul24(a, b) : a * b) & mask; };
-  auto bucket = [&](uint32_t l, uint32_t f) -> uint32_t {
-    if (NDIM == 1) return ((mulmod(s_sig[l][0], f) + c) & mask) >> logW;
-    const uint32_t f1 = f >> logn, f2 = f & mask;
-    const uint32_t h1 = ((mulmod(s_sig[l][0], f1) + c) & mask) >> logW;
-    const uint32_t h2 = ((mulmod(s_sig[l][1], f2) + c) & mask) >> logW;
-    return (h1 << logB) | h2;
+  // bucket of f along one axis: bits logW .. logn - 1 of sigma f + c, the
+  // product taken modulo 2^32
+  auto axis = [&](uint32_t sg, uint32_t f) -> uint32_t {
+    return __builtin_amdgcn_ubfe((SMALL ? __umul24(sg, f) : sg * f) + c, logW, logB);
   };
-  auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t { return (s_bits[l * words + (h >> 5)] >> (h & 31u)) & 1u; };
+  auto bucket = [&](uint32_t l, uint32_t f) -> uint32_t {
+    if (NDIM == 1) return axis(s_sig[l][0], f);
+    return (axis(s_sig[l][0], f >> logn) << logB) | axis(s_sig[l][1], f & mask);
+  };
+  // the bit extract takes the bit index modulo 32 by itself
+  auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t {
+    return __builtin_amdgcn_ubfe(s_bits[l * words + (h >> 5)], h, 1u);
+  };
   // the m-th loop other than e
   auto other = [&](uint32_t m) -> uint32_t { return m < e ? m : m + 1u; };
   // a candidate with all its votes counted: emitted unless an earlier
@@ -1476,10 +1481,6 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
       }
 #pragma unroll
       for (uint32_t k = 0; k < KB * KB; ++k) v[k] = real ? 0u : 0x80000000u;
-      // axis bucket: the product modulo 2^32, then modulo n
-      auto axis = [&](uint32_t sg, uint32_t f) -> uint32_t {
-        return (((SMALL ? __umul24(sg, f) : sg * f) + c) & mask) >> logW;
-      };
       if (logB >= 5u) {
         // a bitmap row is whole words: byte offsets of row h1's words and of
         // h2's word within a row, and h2's bit
@@ -1491,16 +1492,15 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
 #pragma unroll
           for (uint32_t a = 0; a < KB; ++a) {
             r[a] = (l * words + (axis(s1, f1[a]) << (logB - 5u))) << 2;
-            const uint32_t h2 = axis(s2, f2[a]);
-            w2[a] = (h2 >> 5) << 2;
-            t2[a] = h2 & 31u;
+            t2[a] = axis(s2, f2[a]);
+            w2[a] = (t2[a] >> 5) << 2;
           }
 #pragma unroll
           for (uint32_t a = 0; a < KB; ++a) {
 #pragma unroll
             for (uint32_t bb = 0; bb < KB; ++bb) {
               const uint32_t word = *reinterpret_cast<const uint32_t *>(bits + r[a] + w2[bb]);
-              v[a * KB + bb] += (word >> t2[bb]) & 1u;
+              v[a * KB + bb] += __builtin_amdgcn_ubfe(word, t2[bb], 1u);
             }
           }
         }
@@ -1520,7 +1520,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
 #pragma unroll
             for (uint32_t bb = 0; bb < KB; ++bb) {
               const uint32_t hb = r[a] + h2[bb];
-              v[a * KB + bb] += (s_bits[hb >> 5] >> (hb & 31u)) & 1u;
+              v[a * KB + bb] += __builtin_amdgcn_ubfe(s_bits[hb >> 5], hb, 1u);
             }
           }
         }
