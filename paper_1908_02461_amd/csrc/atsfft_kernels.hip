@@ -173,6 +173,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// Set bits of a wave mask in the lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Sum over the block; `sh` is one LDS word.  Every thread gets the total.
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
   if (threadIdx.x == 0) *sh = 0;
@@ -1182,8 +1187,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     kmax = max(kmax, other);
   }
   R *ms = reinterpret_cast<R *>(smem);
-  unsigned char *flags = smem + (size_t)Bc * sizeof(R);
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + Bc + 15) & ~(size_t)15));
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + 15) & ~(size_t)15));
   uint32_t *sh = hist + 512;               // 32 words of scratch
   K *wmax = reinterpret_cast<K *>(sh + 32);  // one key per wave
   __syncthreads();
@@ -1270,63 +1274,103 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     return;
   }
 
-  // location loop: J = the min(num, #{m > T}) largest keys above T
+  // location loop: J = the min(num, #{m > T}) largest keys above T.  Taken
+  // are the buckets above v, and of those equal to v the first `need` in
+  // index order (v = T and need = 0 when all above T fit).  A thread's keys
+  // are still in mv; the list is built in index order from 64-bucket chunks,
+  // one wave ballot each, so no LDS pass runs over a thread's own chunk.
   uint32_t above = 0;
-  for (uint32_t b = tid; b < Bc; b += T) above += ms[b] > Tr ? 1u : 0u;
+#pragma unroll
+  for (int j = 0; j < kBucketMaxPer; ++j) {
+    const uint32_t b = tid + (uint32_t)j * T;
+    above += (uint32_t)j < per && b < Bc && mv[j] > Tr ? 1u : 0u;
+  }
   const uint32_t n_above = block_sum(above, &sh[4]);
   uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
   if (num > Bc) num = Bc;
-  // contiguous chunk per thread so that selections come out in index order
-  const uint32_t start = tid * per;
-  const uint32_t cnt = start < Bc ? min(per, Bc - start) : 0u;
-  uint32_t mine = 0;
-  if (n_above <= num) {
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const unsigned char f = ms[start + j] > Tr ? 1 : 0;
-      flags[start + j] = f;
-      mine += f;
-    }
-  } else {
+  R v = Tr;
+  uint32_t need = 0;
+  if (n_above > num) {
     // the num-th largest: among the n_above values above T, the
     // (n_above - num)-th smallest
-    const R v = block_kth_smallest<R>(ms, Bc, n_above - num, hist, sh, Tr);
-    uint32_t gt = 0, ties = 0;
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const R mj = ms[start + j];
-      gt += mj > v ? 1u : 0u;
-      ties += mj == v ? 1u : 0u;
+    v = block_kth_smallest<R>(ms, Bc, n_above - num, hist, sh, Tr);
+    uint32_t gt = 0;
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = tid + (uint32_t)j * T;
+      gt += (uint32_t)j < per && b < Bc && mv[j] > v ? 1u : 0u;
     }
-    const uint32_t n_gt = block_sum(gt, &sh[4]);
-    uint32_t tot;
-    uint32_t rank = block_excl_scan(ties, sh + 8, &tot);
-    const uint32_t need = num - n_gt;
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const R mj = ms[start + j];
-      unsigned char f = 0;
-      if (mj > v) {
-        f = 1;
-      } else if (mj == v) {
-        f = rank < need ? 1 : 0;
-        ++rank;
+    need = num - block_sum(gt, &sh[4]);
+  }
+  // per chunk (Bc / 64 <= 256 of them): buckets above v, buckets equal to v
+  const uint32_t lane = tid & 63u;
+  uint32_t *cg = hist, *ce = hist + 256;
+#pragma unroll
+  for (int j = 0; j < kBucketMaxPer; ++j) {
+    if ((uint32_t)j < per) {  // uniform over the block
+      const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
+      const unsigned long long g = __ballot(b < Bc && mv[j] > v);
+      const unsigned long long e = __ballot(b < Bc && need > 0u && mv[j] == v);
+      if (lane == 0 && b0 < Bc) {
+        cg[b0 >> 6] = (uint32_t)__popcll(g);
+        ce[b0 >> 6] = (uint32_t)__popcll(e);
       }
-      flags[start + j] = f;
-      mine += f;
     }
   }
-  uint32_t total;
-  uint32_t pos = block_excl_scan(mine, sh + 8, &total);
-  int32_t *jl = jlist_of(P, sig, loop);
-  for (uint32_t j = 0; j < cnt; ++j)
-    if (flags[start + j]) jl[pos++] = (int32_t)(start + j);
   __syncthreads();
-  // the cutoff bitmap, 64 buckets per wave ballot
+  if (tid < 64) {
+    // one wave scans the chunks, four per lane: ties before each chunk, then
+    // list positions (the chunk's taken ties are the first `need` overall)
+    const uint32_t nch = (Bc + 63u) >> 6;
+    uint32_t g4[4], e4[4], te[4], sel[4], es = 0, ss = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t c = 4u * tid + (uint32_t)i;
+      g4[i] = c < nch ? cg[c] : 0u;
+      e4[i] = c < nch ? ce[c] : 0u;
+      es += e4[i];
+    }
+    uint32_t run = wave_incl_scan(es) - es;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      te[i] = run;
+      run += e4[i];
+      sel[i] = g4[i] + min(e4[i], need > te[i] ? need - te[i] : 0u);
+      ss += sel[i];
+    }
+    const uint32_t incl = wave_incl_scan(ss);
+    run = incl - ss;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t c = 4u * tid + (uint32_t)i;
+      if (c < nch) {
+        cg[c] = run;
+        ce[c] = te[i];
+      }
+      run += sel[i];
+    }
+    if (tid == 63) sh[6] = incl;
+  }
+  __syncthreads();
+  const uint32_t total = sh[6];
+  // the list in index order and the cutoff bitmap, one ballot per chunk
+  int32_t *jl = jlist_of(P, sig, loop);
   uint32_t *jb = jbits_of(P, sig, loop);
-  for (uint32_t b0 = tid & ~63u; b0 < Bc; b0 += T) {
-    const uint32_t b = b0 + (tid & 63u);
-    const unsigned long long bits = __ballot(b < Bc && flags[b]);
-    if ((tid & 63u) == 0) {
-      jb[b0 >> 5] = (uint32_t)bits;
-      if (b0 + 32 < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(bits >> 32);
+#pragma unroll
+  for (int j = 0; j < kBucketMaxPer; ++j) {
+    if ((uint32_t)j < per) {  // uniform over the block
+      const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
+      const bool ok = b < Bc;
+      const bool eq = ok && need > 0u && mv[j] == v;
+      const unsigned long long e = __ballot(eq);
+      const uint32_t c = b0 >> 6;
+      const bool f = (ok && mv[j] > v) || (eq && ce[c] + lanes_below(e) < need);
+      const unsigned long long fm = __ballot(f);
+      if (f) jl[cg[c] + lanes_below(fm)] = (int32_t)b;
+      if (lane == 0 && b0 < Bc) {
+        jb[b0 >> 5] = (uint32_t)fm;
+        if (b0 + 32u < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(fm >> 32);
+      }
     }
   }
   if (tid == 0) {
@@ -2194,7 +2238,7 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
   const size_t fft = 2 * rs * (Bc_max + Bc_max / 32);  // one pad element per 32
-  const size_t sel = ((rs * Bc_max + Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
+  const size_t sel = ((rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
 
