@@ -192,6 +192,8 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  *   ATSFFT_ROWS2D        2D main-loop hash: 0 slab gather, 1 per bucket row,
  *                        2 rows streamed once; only lowers the plan's form (2)
  *   ATSFFT_STREAM_ROWS   rows per workgroup of the streamed 2D hash, 1..64 (2)
+ *   ATSFFT_GATHER_LDS    0: the adjoint gather reads bucket adjoints from
+ *                        device memory instead of staging them in LDS
  */
 atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d);
 

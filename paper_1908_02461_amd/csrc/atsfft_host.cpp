@@ -31,6 +31,7 @@ struct atsfft_plan_s {
   uint32_t vote_blocks; // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;   // 2D main loops may be hashed by rows staged in LDS
   uint32_t stream_rows; // 2D streamed row hash: rows per workgroup
+  uint32_t gather_lds;  // adjoint gather: most LDS bytes for a staged bucket adjoint (0: none)
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
@@ -281,6 +282,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.vote_blocks = plan->vote_blocks;
   P.rows2d_ok = plan->rows2d_ok;
   P.stream_rows = plan->stream_rows;
+  P.gather_lds = plan->gather_lds;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
   P.tile_slots = plan->tile_slots;
@@ -437,6 +439,11 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   if (const char *env = std::getenv("ATSFFT_STREAM_ROWS")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->stream_rows = (uint32_t)v;
+  }
+  p->gather_lds = (uint32_t)kGatherLdsBytes;
+  if (const char *env = std::getenv("ATSFFT_GATHER_LDS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v == 0) p->gather_lds = 0;
   }
   if (const char *env = std::getenv("ATSFFT_VOTE_BLOCKS")) {
     const long v = std::strtol(env, nullptr, 10);

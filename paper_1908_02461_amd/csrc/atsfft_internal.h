@@ -17,8 +17,9 @@ constexpr int kVoteThreads = 256;
 constexpr int kEstThreads = 256;
 constexpr int kEstGroups = 4;          // estimate workgroups per signal
 constexpr uint32_t kEstRankMax = 1024; // located sets up to this size are sorted by rank
-constexpr int kGatherThreads = 256;  // adjoint gather: threads per block
-constexpr int kGatherPer = 4;        // addresses per thread and pass
+constexpr int kGatherThreads = 1024;  // adjoint gather: threads per block
+constexpr int kGatherPer = 16;        // addresses per thread and pass
+constexpr size_t kGatherLdsBytes = 65536;  // adjoint gather: most LDS for a staged bucket adjoint
 constexpr int kRowTaps = 8;                // 2D row hash: column wraps per thread, at most
 constexpr uint32_t kRowBytes = 64u << 10;  // 2D row hash: largest row staged in LDS
 constexpr int kMaxOut = 16384;
@@ -81,6 +82,7 @@ struct KParams {
   uint32_t rows2d_ok;    // 2D main-loop hash by rows allowed: 0 no, 1 per bucket row, 2 streamed (plan)
   uint32_t rows2d;       // the form this launch sequence uses (0, 1 or 2)
   uint32_t stream_rows;  // streamed form: rows per workgroup
+  uint32_t gather_lds;   // adjoint gather: most LDS bytes for a staged bucket adjoint (0: none)
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels

@@ -2088,13 +2088,24 @@ __global__ __launch_bounds__(kBucketThreads) void k_bwd_bucket(KParams P, const 
 // The scatter grad_x[sigma_l t + tau_l] += G_t u_l[t mod B], done as a gather:
 // within one loop t -> sigma_l t + tau_l is a bijection of Z_n (sigma_l odd),
 // so address a is reached by the single tap t = sigma_l^{-1} (a - tau_l) at
-// most, and only when t lies in the window.  Each thread owns kGatherPer
+// most, and only when t lies in the window.  Each thread owns gather_per
 // addresses, sums its loops in index order and writes every address once,
 // zero included: no atomics, no separate clearing pass, and the same result
 // on every run.  For 2D the tap test splits per axis (row, then column).
+// A hit costs two random loads, the tap and the bucket adjoint; when a loop's
+// bucket adjoint fits the workgroup's LDS (`lds` bytes) it is staged there
+// with coalesced loads first, which leaves one random load per hit.
+// addresses per thread (measured for the 1D FP32 gather at n = 2^20, B = 4096:
+// 8, 16 and 32 addresses 791, 632 and 673 us); FP64 takes half as many to stay
+// within the registers
+template <typename R, int NDIM> constexpr int gather_per() { return sizeof(R) == 4 ? kGatherPer : kGatherPer / 2; }
+
 template <typename R, int NDIM>
-__global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *grad_x) {
+__global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *grad_x, uint32_t lds) {
   using C = typename CT<R>::C;
+  constexpr int PER = gather_per<R, NDIM>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *su = reinterpret_cast<C *>(smem);
   const uint32_t sig = blockIdx.y;
   __shared__ uint32_t s_inv[kMaxLoops][2], s_tau[kMaxLoops][2];
   __shared__ const C *s_u[kMaxLoops];
@@ -2119,21 +2130,29 @@ __global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *
   const uint32_t nl = s_nl;
   const uint32_t B = (uint32_t)state_of(P, sig)->B_star;
   const uint32_t logB = ilog2(B);
+  const uint32_t Bc = NDIM == 1 ? B : B * B;
+  const bool staged = (size_t)Bc * sizeof(C) <= (size_t)lds;  // uniform over the workgroup
   const uint32_t n = P.n, mask = n - 1u;
   const uint32_t w = min(P.alpha * B, n), half = w >> 1;
   const R *G = nl ? taps_of<R>(P, 1, logB) : nullptr;
   C *gx = reinterpret_cast<C *>(grad_x) + (int64_t)sig * P.x_sig;
   const uint32_t total = (uint32_t)P.x_sig;
-  const uint32_t span = kGatherThreads * kGatherPer;
+  const uint32_t span = kGatherThreads * PER;
   for (uint32_t base = blockIdx.x * span; base < total; base += gridDim.x * span) {
-    R acc_re[kGatherPer], acc_im[kGatherPer];
+    R acc_re[PER], acc_im[PER];
 #pragma unroll
-    for (int j = 0; j < kGatherPer; ++j) acc_re[j] = acc_im[j] = (R)0;
+    for (int j = 0; j < PER; ++j) acc_re[j] = acc_im[j] = (R)0;
     for (uint32_t q = 0; q < nl; ++q) {
       const C *u = s_u[q];
+      if (staged) {
+        __syncthreads();  // the previous loop's reads are done
+        for (uint32_t b = threadIdx.x; b < Bc; b += kGatherThreads) su[b] = u[b];
+        __syncthreads();
+        u = su;
+      }
       if (NDIM == 1) {
 #pragma unroll
-        for (int j = 0; j < kGatherPer; ++j) {
+        for (int j = 0; j < PER; ++j) {
           const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
           const uint32_t i = (s_inv[q][0] * (a - s_tau[q][0]) + half) & mask;
           if (i < w) {
@@ -2145,7 +2164,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < kGatherPer; ++j) {
+        for (int j = 0; j < PER; ++j) {
           const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
           const uint32_t a1 = a >> P.logn, a2 = a & mask;
           const uint32_t i1 = (s_inv[q][0] * (a1 - s_tau[q][0]) + half) & mask;
@@ -2160,7 +2179,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_bwd_gather(KParams P, void *
       }
     }
 #pragma unroll
-    for (int j = 0; j < kGatherPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
       const uint32_t a = base + (uint32_t)j * kGatherThreads + threadIdx.x;
       if (a < total) {
         C o;
@@ -2176,9 +2195,11 @@ template <typename R, int NDIM>
 static hipError_t run_backward(const KParams &P, int batch, const void *grad_vals, void *grad_x, hipStream_t s) {
   const size_t smem = bwd_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max, P.max_out);
   hipLaunchKernelGGL((k_bwd_bucket<R, NDIM>), dim3(P.L_est, batch), dim3(kBucketThreads), smem, s, P, grad_vals);
-  const uint32_t span = kGatherThreads * kGatherPer;
+  const uint32_t span = kGatherThreads * gather_per<R, NDIM>();
   const uint32_t blocks = (uint32_t)std::min<int64_t>((P.x_sig + span - 1) / span, 1024);
-  hipLaunchKernelGGL((k_bwd_gather<R, NDIM>), dim3(blocks, batch), dim3(kGatherThreads), 0, s, P, grad_x);
+  const size_t lds = std::min<size_t>((size_t)P.Bc_max * 2 * sizeof(R), P.gather_lds);
+  hipLaunchKernelGGL((k_bwd_gather<R, NDIM>), dim3(blocks, batch), dim3(kGatherThreads), lds, s, P, grad_x,
+                     (uint32_t)lds);
   return hipGetLastError();
 }
 
@@ -2266,6 +2287,9 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
   // most the bucket kernel's LDS plus 256 bytes
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_residual<R, NDIM>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bucket + 256));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_gather<R, NDIM>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGatherLdsBytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hash2d_rows<R>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowBytes);

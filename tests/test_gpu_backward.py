@@ -160,3 +160,32 @@ def test_backward_of_empty_signal_is_zero(A):
     assert int(status[0]) & A.SIG_EMPTY
     (vals.abs() ** 2).sum().backward()
     assert torch.count_nonzero(xd.grad) == 0
+
+
+@pytest.mark.parametrize("ndim,n,k", [(1, 1 << 16, 12), (2, 256, 6)])
+def test_gather_staged_equals_unstaged(A, monkeypatch, ndim, n, k):
+    """The adjoint gather with each loop's bucket adjoint staged in LDS gives
+    the gradient it gives with every read from device memory
+    (ATSFFT_GATHER_LDS=0): the loops are added in the same order either way,
+    and only the bucket cotangent's atomic adds of located frequencies that
+    share a bucket may reorder between calls."""
+    import torch
+
+    make = synth.planted_1d if ndim == 1 else synth.planted_2d
+    x = make(n, k, 12, mag=("uniform", 0.5, 1.0), snr_db=40.0, dtype=np.complex64)[0]
+    grads = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("ATSFFT_GATHER_LDS", raising=False)
+        else:
+            monkeypatch.setenv("ATSFFT_GATHER_LDS", env)
+        plan = A.Plan(ndim, n, "c64", seed=29)
+        xd = torch.from_numpy(x[None].copy()).cuda().requires_grad_(True)
+        vals, locs, count, khat, status = A.sparse_fft(xd, plan)
+        cnt = int(count[0])
+        assert cnt > 0
+        w = torch.linspace(0.5, 1.5, cnt, device="cuda").to(torch.complex64)
+        (torch.abs(vals[0, :cnt] * w) ** 2).sum().backward()
+        grads.append(xd.grad.detach().cpu().numpy())
+    assert np.count_nonzero(grads[0]) > 0
+    assert np.max(np.abs(grads[0] - grads[1])) <= 1e-6 * np.max(np.abs(grads[0]))
