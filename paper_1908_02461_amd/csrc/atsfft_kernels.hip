@@ -340,7 +340,6 @@ __global__ void k_init(KParams P, int batch) {
 // slab's partial y_b.  k_bucket adds the kSlabs partials in slab order.
 constexpr int kTile = 64;        // buckets per tile
 constexpr int kVoteIlp = 4;      // vote candidates tested together
-constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x column preimages
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
@@ -1381,6 +1380,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
 
 // -------------------------------------------------------------- k_vote ----
 
+constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x column preimages
+
 // Reverse hash and vote (Algorithm 1/2): votes(f) = #{l : h_l(f) in J_l},
 // S = {f : votes >= T_vote}.  Any f in S is in J_l for at least one of the
 // first E = L_loc - T_vote + 1 loops, so the candidates are the preimages of
@@ -1650,36 +1651,16 @@ __device__ __forceinline__ EstTerm<R> est_term(const uint32_t *es, uint32_t f, u
   return t;
 }
 
-template <typename R, int N> __device__ __forceinline__ void sort_net(R (&a)[N]) {
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int l = i ^ j;
-        if (l > i) {
-          const R x = a[i], y = a[l];
-          const R lo = x < y ? x : y, hi = x < y ? y : x;
-          if ((i & k) == 0) {
-            a[i] = lo;
-            a[l] = hi;
-          } else {
-            a[i] = hi;
-            a[l] = lo;
-          }
-        }
-      }
-    }
-  }
-}
-
 // Sort S ascending, then for each located f and estimation loop l the
 // estimator display: e_l(f) = y_hat_l[h_l(f)] omega^{tau_l f} / G'(o_l(f)),
 // and the coordinate-wise median over the L_est loops.  The kEstGroups
 // workgroups of a signal each sort S (by rank when |S| <= kEstRankMax: the
-// entries are distinct, so each lands at the count of smaller ones) and take
-// every kEstGroups-th block of kEstThreads located frequencies.
+// entries are distinct, so each lands at the count of smaller ones).  ML
+// lanes (a power of two >= L_est) take one located frequency, one loop each,
+// so that the loops' loads and arithmetic run side by side; the median of
+// the real parts is the value whose rank among the lanes' (ties by loop
+// order, unused lanes +inf) is L_est / 2, and likewise for the imaginary
+// parts.
 template <typename R, int NDIM, int ML>
 __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   using C = typename CT<R>::C;
@@ -1763,58 +1744,46 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
   // the sorted set goes to its own array: every workgroup reads S above
   uint32_t *Sg = Ssort_of(P, sig);
   uint16_t *tape = tape_of(P, sig);
-  for (uint32_t i = grp * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+  const uint32_t l = threadIdx.x & (uint32_t)(ML - 1);  // this lane's loop
+  const uint32_t per = (gridDim.x * blockDim.x) / (uint32_t)ML;
+  // a group's lanes share i, so each group leaves the loop as one
+  for (uint32_t i = (grp * blockDim.x + threadIdx.x) / (uint32_t)ML; i < count; i += per) {
     const uint32_t f = sS[i];
-    R re[ML], im[ML], re0[ML], im0[ML];
-    // every loop's bucket value and window factor are loaded before any is
-    // used (slots past L_est repeat the last loop and are discarded)
-    EstTerm<R> t[ML];
-    C yv[ML];
-#pragma unroll
-    for (int l = 0; l < ML; ++l) {
-      const uint32_t lc = min((uint32_t)l, Le - 1u);
-      t[l] = est_term<R, NDIM>(es[lc], f, n, logn, logB, logW, c, gh);
-      yv[l] = ymain_of<C>(P, sig, P.L_loc + lc)[t[l].h];
+    R re = (R)INFINITY, im = (R)INFINITY;
+    if (l < Le) {
+      const EstTerm<R> t = est_term<R, NDIM>(es[l], f, n, logn, logB, logW, c, gh);
+      const C yv = ymain_of<C>(P, sig, P.L_loc + l)[t.h];
+      R sn, cs;
+      sincos_pi(-(R)t.phase * two_over_n, &sn, &cs);
+      const R zr = yv.x * cs - yv.y * sn;
+      const R zi = yv.x * sn + yv.y * cs;
+      re = zr / t.g;
+      im = zi / t.g;
     }
+    // ranks among the group's lanes, ties broken by loop index
+    uint32_t rre = 0, rim = 0;
 #pragma unroll
-    for (int l = 0; l < ML; ++l) {
-      re[l] = (R)INFINITY;
-      im[l] = (R)INFINITY;
-      if ((uint32_t)l < Le) {
-        R sn, cs;
-        sincos_pi(-(R)t[l].phase * two_over_n, &sn, &cs);
-        const R zr = yv[l].x * cs - yv[l].y * sn;
-        const R zi = yv[l].x * sn + yv[l].y * cs;
-        re[l] = zr / t[l].g;
-        im[l] = zi / t[l].g;
-      }
-      re0[l] = re[l];
-      im0[l] = im[l];
+    for (int j = 0; j < ML; ++j) {
+      const R oj = __shfl(re, j, ML), pj = __shfl(im, j, ML);
+      rre += (oj < re || (oj == re && (uint32_t)j < l)) ? 1u : 0u;
+      rim += (pj < im || (pj == im && (uint32_t)j < l)) ? 1u : 0u;
     }
-    sort_net<R, ML>(re);
-    sort_net<R, ML>(im);
+    // the medians, and the first loop holding each (the adjoint's tape)
+    const uint32_t gbase = threadIdx.x & 63u & ~(uint32_t)(ML - 1);
+    const unsigned long long gmask = (ML == 64 ? ~0ull : ((1ull << ML) - 1ull)) << gbase;
+    const uint32_t src_re = (uint32_t)__ffsll((long long)(__ballot(rre == Le / 2u) & gmask)) - 1u - gbase;
+    const uint32_t src_im = (uint32_t)__ffsll((long long)(__ballot(rim == Le / 2u) & gmask)) - 1u - gbase;
     C v;
-    v.x = re[Le / 2];
-    v.y = im[Le / 2];
-    // the loops whose estimates are the medians (the first on ties): the
-    // tape of the adjoint
-    uint32_t lre = 0, lim = 0;
-    bool fre = false, fim = false;
-#pragma unroll
-    for (int l = 0; l < ML; ++l) {
-      if (!fre && (uint32_t)l < Le && re0[l] == v.x) {
-        fre = true;
-        lre = (uint32_t)l;
-      }
-      if (!fim && (uint32_t)l < Le && im0[l] == v.y) {
-        fim = true;
-        lim = (uint32_t)l;
-      }
+    v.x = __shfl(re, (int)src_re, ML);
+    v.y = __shfl(im, (int)src_im, ML);
+    const uint32_t lre = (uint32_t)__ffsll((long long)(__ballot(re == v.x) & gmask)) - 1u - gbase;
+    const uint32_t lim = (uint32_t)__ffsll((long long)(__ballot(im == v.y) & gmask)) - 1u - gbase;
+    if (l == 0) {
+      locs[i] = (int64_t)f;
+      vals[i] = v;
+      Sg[i] = f;
+      tape[i] = (uint16_t)(lre | (lim << 8));
     }
-    locs[i] = (int64_t)f;
-    vals[i] = v;
-    Sg[i] = f;
-    tape[i] = (uint16_t)(lre | (lim << 8));
   }
 }
 
