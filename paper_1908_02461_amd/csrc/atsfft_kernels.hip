@@ -1106,8 +1106,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     return (bitrev(b >> logB, logB) << logB) | bitrev(b & (B - 1u), logB);
   };
   // the partials are added in slab (or row-wrap) order: the streamed 2D row
-  // hash leaves one per row wrap (slots past the last wrap are read, they lie
-  // in the array, but not used), the row hash one in all, k_hash kSlabs; the
+  // hash leaves one per row wrap, the row hash one in all, k_hash kSlabs; the
   // compensated FP32 fold adds them in FP64.  kSumU buckets per thread have
   // their loads issued together.
   const uint32_t nsl = !main_phase ? (NDIM == 1 ? (uint32_t)kSlabs : 1u)
@@ -1124,7 +1123,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
       for (int sl = 0; sl < kSlabs; ++sl) {
         u[k][sl].x = 0;
         u[k][sl].y = 0;
-        if (b < Bc && (sl == 0 || nsl > 1u)) u[k][sl] = yg[(size_t)sl * sstride + b];
+        if (b < Bc && (uint32_t)sl < nsl) u[k][sl] = yg[(size_t)sl * sstride + b];
       }
     }
 #pragma unroll
