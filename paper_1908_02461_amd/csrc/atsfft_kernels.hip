@@ -1652,9 +1652,10 @@ __device__ __forceinline__ EstTerm<R> est_term(const uint32_t *es, uint32_t f, u
 
 // Sort S ascending, then for each located f and estimation loop l the
 // estimator display: e_l(f) = y_hat_l[h_l(f)] omega^{tau_l f} / G'(o_l(f)),
-// and the coordinate-wise median over the L_est loops.  The kEstGroups
-// workgroups of a signal each sort S (by rank when |S| <= kEstRankMax: the
-// entries are distinct, so each lands at the count of smaller ones).  ML
+// and the coordinate-wise median over the L_est loops.  The workgroups of a
+// signal (kEstGroups, more for small batches) each sort S (by rank when
+// |S| <= kEstRankMax: the entries are distinct, so each lands at the count of
+// smaller ones).  ML
 // lanes (a power of two >= L_est) take one located frequency, one loop each,
 // so that the loops' loads and arithmetic run side by side; the median of
 // the real parts is the value whose rank among the lanes' (ties by loop
@@ -2375,12 +2376,14 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     else
       hipLaunchKernelGGL((k_vote<NDIM, false>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
     if (marks && mark) mark(ctx, 4);
+    // estimate workgroups per signal: more for small batches, up to 32
+    const uint32_t est_groups = std::min<uint32_t>(32u, std::max<uint32_t>((uint32_t)kEstGroups, 128u / (uint32_t)batch));
     if (Q.L_est <= 8)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
     else if (Q.L_est <= 16)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
     else
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(kEstGroups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
   };
   main_pass(P, true);
   if (P.res_tol > 0.0) {
