@@ -1234,21 +1234,47 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
           for (int j = 0; j < 4; ++j) v[i][1 + j] = rowp[c0 + (uint32_t)j];
           v[i][5] = rowp[(c0 + 4u) & (B - 1u)];
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const R mb = v[1][1 + j];
-          const uint32_t b = ridx[1] | (c0 + (uint32_t)j);
-          bool is_max = mb > Tr;
+        if constexpr (sizeof(R) == 4) {
+          // (m, -index) as one 64-bit key: m_b > m_n, or m_b = m_n with b < n,
+          // is key_b > key_n (m >= 0, so its bit pattern orders like m)
+          unsigned long long kk[3][6];
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-              if (i == 1 && dj == 0) continue;
-              const R mn = v[i][1 + j + dj];
-              const uint32_t nb = ridx[i] | ((c0 + (uint32_t)(j + dj)) & (B - 1u));
-              is_max = is_max & (mb > mn || (mb == mn && b < nb));
+            for (int j = 0; j < 6; ++j) {
+              const uint32_t idx = ridx[i] | ((c0 + (uint32_t)j - 1u) & (B - 1u));
+              kk[i][j] = ((unsigned long long)key_of(v[i][j]) << 32) | (0xFFFFFFFFu - idx);
             }
-          c += is_max ? 1u : 0u;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned long long kb = kk[1][1 + j];
+            bool is_max = v[1][1 + j] > Tr;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int dj = -1; dj <= 1; ++dj) {
+                if (i == 1 && dj == 0) continue;
+                is_max = is_max & (kb > kk[i][1 + j + dj]);
+              }
+            c += is_max ? 1u : 0u;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const R mb = v[1][1 + j];
+            const uint32_t b = ridx[1] | (c0 + (uint32_t)j);
+            bool is_max = mb > Tr;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int dj = -1; dj <= 1; ++dj) {
+                if (i == 1 && dj == 0) continue;
+                const R mn = v[i][1 + j + dj];
+                const uint32_t nb = ridx[i] | ((c0 + (uint32_t)(j + dj)) & (B - 1u));
+                is_max = is_max & (mb > mn || (mb == mn && b < nb));
+              }
+            c += is_max ? 1u : 0u;
+          }
         }
       }
     }
