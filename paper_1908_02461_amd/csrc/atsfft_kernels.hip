@@ -1185,7 +1185,9 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     kmax = max(kmax, other);
   }
   R *ms = reinterpret_cast<R *>(smem);
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + 15) & ~(size_t)15));
+  // LDS after the DFT: m, room for the keys above T, then the select's scratch
+  R *above_keys = reinterpret_cast<R *>(smem + (((size_t)Bc * sizeof(R) + 15) & ~(size_t)15));
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)2 * Bc * sizeof(R) + 15) & ~(size_t)15));
   uint32_t *sh = hist + 512;               // 32 words of scratch
   K *wmax = reinterpret_cast<K *>(sh + 32);  // one key per wave
   __syncthreads();
@@ -1309,6 +1311,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
     const uint32_t b = tid + (uint32_t)j * T;
     above += (uint32_t)j < per && b < Bc && mv[j] > Tr ? 1u : 0u;
   }
+  if (tid == 0) sh[7] = 0;  // the count of keys above T gathered below
   const uint32_t n_above = block_sum(above, &sh[4]);
   uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
   if (num > Bc) num = Bc;
@@ -1316,8 +1319,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   uint32_t need = 0;
   if (n_above > num) {
     // the num-th largest: among the n_above values above T, the
-    // (n_above - num)-th smallest
-    v = block_kth_smallest<R>(ms, Bc, n_above - num, hist, sh, Tr);
+    // (n_above - num)-th smallest, selected from those values gathered into
+    // their own LDS array (in any order) so that the radix passes scan only them
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = tid + (uint32_t)j * T;
+      if ((uint32_t)j < per && b < Bc && mv[j] > Tr) above_keys[atomicAdd(&sh[7], 1u)] = mv[j];
+    }
+    __syncthreads();
+    v = block_kth_smallest<R>(above_keys, n_above, n_above - num, hist, sh);
     uint32_t gt = 0;
 #pragma unroll
     for (int j = 0; j < kBucketMaxPer; ++j) {
@@ -2254,7 +2264,7 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
   const size_t fft = 2 * rs * (Bc_max + Bc_max / 32);  // one pad element per 32
-  const size_t sel = ((rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
+  const size_t sel = ((2 * rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
 
