@@ -190,28 +190,6 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
   return r;
 }
 
-// Exclusive prefix sum in thread order; `sh` holds 17 LDS words.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  uint32_t incl = wave_incl_scan(v);
-  if (lane == 63) sh[wv] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < nw; ++i) {
-      uint32_t t = sh[i];
-      sh[i] = run;
-      run += t;
-    }
-    sh[16] = run;
-  }
-  __syncthreads();
-  uint32_t r = sh[wv] + incl - v;
-  *total = sh[16];
-  __syncthreads();
-  return r;
-}
-
 // The k-th smallest (0-based) of the values of m[0..cnt) in LDS that exceed
 // `above` (default: all), by most-significant-digit radix selection on the
 // bit patterns (the values are non-negative, so their patterns order like the
