@@ -193,30 +193,42 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
 // The k-th smallest (0-based) of the values of m[0..cnt) in LDS that exceed
 // `above` (default: all), by most-significant-digit radix selection on the
 // bit patterns (the values are non-negative, so their patterns order like the
-// values).  `hist` has 2 x 256 words, used in turn so
+// values).  When the keys' range [lo, hi] is known, the digits are taken of
+// key - lo from the top bit of hi - lo, so that the first pass spreads the
+// keys over all 256 bins instead of the few that the exponent's top bits
+// give.  `hist` has 2 x 256 words, used in turn so
 // that each pass clears the next pass's histogram while it counts; `sh` has 4
 // words (the chosen digit and rank, also in turn).
+__device__ __forceinline__ int bit_length(uint32_t v) { return v ? 32 - __clz((int)v) : 0; }
+__device__ __forceinline__ int bit_length(unsigned long long v) { return v ? 64 - __clzll((long long)v) : 0; }
+
 template <typename R>
 __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
-                                                uint32_t *sh, R above = (R)-1) {
+                                                uint32_t *sh, R above = (R)-1,
+                                                typename CT<R>::K lo = 0,
+                                                typename CT<R>::K hi = ~(typename CT<R>::K)0) {
   using K = typename CT<R>::K;
-  constexpr int NB = sizeof(K) * 8;
+  const int nbits = hi > lo ? bit_length(hi - lo) : 1;
   K prefix = 0, mask = 0;
   for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   int pass = 0;
-  for (int shift = NB - 8; shift >= 0; shift -= 8, ++pass) {
+  for (int top = nbits; top > 0; ++pass) {
+    const int width = top < 8 ? top : 8;
+    const int shift = top - width;
+    top = shift;
+    const uint32_t dmask = (1u << width) - 1u;
     uint32_t *h = hist + 256 * (pass & 1);
     uint32_t *hn = hist + 256 * ((pass + 1) & 1);
     uint32_t *out = sh + 2 * (pass & 1);
     // a thread adds runs of equal digits in one atomic: the leading digits
-    // are shared by most values, and same-address atomics serialise
+    // are shared by many values, and same-address atomics serialise
     uint32_t run_bin = 0, run = 0;
     for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
       const R mb = m[b];
-      const K key = key_of(mb);
+      const K key = key_of(mb) - lo;
       if ((key & mask) == prefix && (above < (R)0 || mb > above)) {
-        const uint32_t bin = (uint32_t)(key >> shift) & 255u;
+        const uint32_t bin = (uint32_t)(key >> shift) & dmask;
         if (run && bin != run_bin) {
           atomicAdd(&h[run_bin], run);
           run = 0;
@@ -226,7 +238,7 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
       }
     }
     if (run) atomicAdd(&h[run_bin], run);
-    if (shift > 0)
+    if (top > 0)
       for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hn[i] = 0;
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -258,10 +270,10 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
     const uint32_t digit = out[0];
     k = out[1];
     prefix |= (K)digit << shift;
-    mask |= (K)255u << shift;
+    mask |= (K)dmask << shift;
   }
   __syncthreads();
-  return val_of(prefix);
+  return val_of(prefix + lo);
 }
 
 // ------------------------------------------------------------- k_init ----
@@ -1145,7 +1157,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   const uint32_t per = (Bc + T - 1) / T;
   const bool stats = !(main_phase && loop >= P.L_loc);
   R mv[kBucketMaxPer];
-  K kmax = 0;
+  K kmax = 0, kmin = ~(K)0;
 #pragma unroll
   for (int j = 0; j < kBucketMaxPer; ++j) {
     const uint32_t b = tid + (uint32_t)j * T;
@@ -1155,12 +1167,14 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
       yg[b] = v;
       mv[j] = v.x * v.x + v.y * v.y;
       kmax = max(kmax, key_of(mv[j]));
+      kmin = min(kmin, key_of(mv[j]));
     }
   }
   if (!stats) return;
   for (int o = 32; o > 0; o >>= 1) {
-    const K other = __shfl_xor(kmax, o);
+    const K other = __shfl_xor(kmax, o), other_min = __shfl_xor(kmin, o);
     kmax = max(kmax, other);
+    kmin = min(kmin, other_min);
   }
   R *ms = reinterpret_cast<R *>(smem);
   // LDS after the DFT: m, room for the keys above T, then the select's scratch
@@ -1168,21 +1182,28 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
   uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)2 * Bc * sizeof(R) + 15) & ~(size_t)15));
   uint32_t *sh = hist + 512;               // 32 words of scratch
   K *wmax = reinterpret_cast<K *>(sh + 32);  // one key per wave
+  K *wmin = wmax + kBucketThreads / 64;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kBucketMaxPer; ++j) {
     const uint32_t b = tid + (uint32_t)j * T;
     if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
   }
-  if ((tid & 63) == 0) wmax[tid >> 6] = kmax;
+  if ((tid & 63) == 0) {
+    wmax[tid >> 6] = kmax;
+    wmin[tid >> 6] = kmin;
+  }
   __syncthreads();
 
   // threshold: noise floor from the floor(q (Bc-1))-th order statistic,
   // c_noise = ln(Bc / noise_rate), and the relative floor rho * max m
-  for (uint32_t wv = 0; wv < (T + 63) / 64; ++wv) kmax = max(kmax, wmax[wv]);
+  for (uint32_t wv = 0; wv < (T + 63) / 64; ++wv) {
+    kmax = max(kmax, wmax[wv]);
+    kmin = min(kmin, wmin[wv]);
+  }
   const R mmax = val_of(kmax);
   const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
-  const R floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh);
+  const R floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh, (R)-1, kmin, kmax);
   const double c_noise = log((double)Bc / P.noise_rate);
   const double t1 = c_noise * ((double)floor_m / P.neg_log1mq);
   const double t2 = P.rho * (double)mmax;
@@ -2242,7 +2263,7 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
   const size_t fft = 2 * rs * (Bc_max + Bc_max / 32);  // one pad element per 32
-  const size_t sel = ((2 * rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 8 * (kBucketThreads / 64);
+  const size_t sel = ((2 * rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 2 * 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
 
