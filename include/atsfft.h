@@ -186,7 +186,8 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  * them changes a result beyond the order of floating-point sums):
  *   ATSFFT_HASH_LOOPS    1D main loops per hash workgroup, 1..3 (1)
  *   ATSFFT_TILE_SLOTS    hash workgroups per slab and loop, 1..64 (32)
- *   ATSFFT_VOTE_BLOCKS   vote workgroups per candidate loop (128 / batch, >= 32)
+ *   ATSFFT_VOTE_BLOCKS   vote workgroups per candidate loop (128 / batch, >= 32;
+ *                        2D: 256 / batch, >= 64)
  *   ATSFFT_PROBE_FIRST   the first probe launch covers B up to this (2048)
  *   ATSFFT_PROBE_STEP    probe levels per later launch, 1..32 (2)
  *   ATSFFT_ROWS2D        2D main-loop hash: 0 slab gather, 1 per bucket row,

@@ -2372,8 +2372,12 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const dim3 hgrid1(hash_blocks, loops, batch);
   const uint32_t E = P.L_loc - P.T_vote + 1;
   // vote workgroups per (loop, signal): more for small batches, where the
-  // launch is latency-bound (a plan knob overrides)
-  const uint32_t vote_blocks = P.vote_blocks ? P.vote_blocks : (uint32_t)max(32, 128 / batch);
+  // launch is latency-bound, and twice as many in 2D, whose blocks of
+  // preimages give a workgroup more candidates (measured at 4096^2, batch 8:
+  // 16, 32, 64, 128 workgroups 67, 63, 60, 68 us; a plan knob overrides)
+  const uint32_t vote_blocks = P.vote_blocks ? P.vote_blocks
+                               : NDIM == 2 ? (uint32_t)max(64, 256 / batch)
+                                           : (uint32_t)max(32, 128 / batch);
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   // 2D rows staged in LDS when the row fits and the input is 16-byte aligned
   const size_t rows_smem = std::max<size_t>((size_t)P.n * sizeof(typename CT<R>::C), 2 * kHashThreads * sizeof(R));
