@@ -15,7 +15,7 @@ constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap grou
 constexpr int kSlabs = 8;            // address slabs of a signal, one per XCD
 constexpr int kVoteThreads = 256;
 constexpr int kEstThreads = 256;
-constexpr int kEstGroups = 8;          // estimate workgroups per signal, at least
+constexpr int kEstGroups = 8;          // estimate workgroups per signal (more for small batches)
 constexpr uint32_t kEstRankMax = 1024; // located sets up to this size are sorted by rank
 constexpr int kGatherThreads = 1024;  // adjoint gather: threads per block
 constexpr int kGatherPer = 16;        // addresses per thread and pass
