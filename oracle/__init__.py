@@ -103,6 +103,19 @@ class _Result(C.Structure):
     ]
 
 
+class _ProbeState(C.Structure):
+    _fields_ = [
+        ("B", C.c_int64),
+        ("k_prev", C.c_int64),
+        ("visited", C.c_uint64),
+        ("iter", C.c_int),
+        ("done", C.c_int),
+        ("status", C.c_int),
+        ("B_star", C.c_int64),
+        ("khat", C.c_int64),
+    ]
+
+
 _D = C.POINTER(C.c_double)
 _I64 = C.POINTER(C.c_int64)
 _U8 = C.POINTER(C.c_uint8)
@@ -158,6 +171,10 @@ def _declare(L):
     L.or_residual.restype = None
     L.or_residual.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_int64, _D, C.c_int, C.c_int, _I64, _I64, _D,
                               C.c_int64, _I64, _D, _D, _D]
+    L.or_probe_init.restype = None
+    L.or_probe_init.argtypes = [C.POINTER(_Params), C.POINTER(_ProbeState)]
+    L.or_probe_step.restype = C.c_int
+    L.or_probe_step.argtypes = [C.POINTER(_Params), C.POINTER(_ProbeState), C.c_int64]
     L.or_atsfft.restype = C.c_int
     L.or_atsfft.argtypes = [C.POINTER(_Params), _D, C.POINTER(_Result)]
 
@@ -383,6 +400,27 @@ class Params:
         for f in fields(Params):
             setattr(p, f.name, getattr(self, f.name))
         return p
+
+
+def probe_run(p: "Params", count_at) -> dict:
+    """Drive the oracle's probe (or_probe_init / or_probe_step, the iteration
+    of Algorithm 2) with given local-maximum counts instead of hashing:
+    count_at maps a bucket count B (per axis) to the count k of the iteration
+    hashed at B (a dict or a callable)."""
+    get = count_at if callable(count_at) else count_at.__getitem__
+    pc = p._c()
+    s = _ProbeState()
+    L = lib()
+    L.or_probe_init(C.byref(pc), C.byref(s))
+    Bs, ks, decs = [], [], []
+    while not s.done:
+        B = int(s.B)
+        k = int(get(B))
+        Bs.append(B)
+        ks.append(k)
+        decs.append(int(L.or_probe_step(C.byref(pc), C.byref(s), k)))
+    return dict(probe_B=Bs, probe_k=ks, probe_decision=decs, B_star=int(s.B_star), khat=int(s.khat),
+                status=int(s.status), n_probe=int(s.iter))
 
 
 def atsfft(x, p: Params, trace: bool = True) -> dict:

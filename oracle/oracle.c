@@ -482,6 +482,85 @@ double or_l1_error(int64_t total, const double *Xtrue, int64_t count, const int6
 /* Algorithm 2                                                               */
 /* ------------------------------------------------------------------------ */
 
+static int64_t bcount(int ndim, int64_t B);
+
+/*
+ * The probe of Algorithm 2 as a state machine, one call per iteration.  The
+ * paper runs a fixed number of iterations and gives no stop rule; the
+ * readings taken here:
+ *   - the first iteration hashes at B0 and always doubles (B1 = 2 B0);
+ *   - later ones apply or_rule to (k_{i-1}, k_i); k_{i-1} = 0 doubles, so
+ *     a run of zero counts keeps doubling;
+ *   - occupancy guard: while B^ndim < gamma k_i the count is not acted on
+ *     and B doubles (gamma = 0: the rule alone, as printed);
+ *   - keep stops at B with khat = k_i;
+ *   - halve stops at B/2 with khat = k_i when B/2 was already hashed, and at
+ *     B (khat = k_i) when B/2 would fall below B0 or below the guard;
+ *     otherwise B halves (on the doubling chain B/2 has always been hashed);
+ *   - doubling past B_max stops at B, PROBE_SATURATED;
+ *   - after P_max iterations without a stop: B and khat of the last one,
+ *     PROBE_NOT_CONVERGED;
+ *   - a probe that ends with khat = 0 is EMPTY.
+ */
+void or_probe_init(const or_params *p, or_probe_state *s) {
+  memset(s, 0, sizeof(*s));
+  s->B = p->B0;
+}
+
+int or_probe_step(const or_params *p, or_probe_state *s, int64_t k) {
+  int64_t B = s->B;
+  int64_t cnt = bcount(p->ndim, B);
+  int lgB = 0;
+  while (((int64_t)1 << lgB) < B) lgB++;
+  s->visited |= (uint64_t)1 << lgB;
+  int dec = (s->iter == 0) ? 1 : or_rule(s->k_prev, k);
+  /* occupancy guard: while fewer than gamma buckets per counted maximum
+     exist, merged neighbours bias the count and the ratio means nothing */
+  if (p->gamma > 0 && cnt < (int64_t)p->gamma * k) dec = 1;
+  s->iter++;
+  int stopped = 0;
+  if (dec == 0) {
+    s->B_star = B;
+    s->khat = k;
+    stopped = 1;
+  } else if (dec < 0) {
+    if (B / 2 < p->B0 || (p->gamma > 0 && bcount(p->ndim, B / 2) < (int64_t)p->gamma * k)) {
+      s->B_star = B;
+      s->khat = k;
+      stopped = 1;
+    } else if (s->visited & ((uint64_t)1 << (lgB - 1))) {
+      s->B_star = B / 2;
+      s->khat = k;
+      stopped = 1;
+    } else {
+      s->B = B / 2;
+    }
+  } else {
+    if (2 * B > p->B_max) {
+      s->B_star = B;
+      s->khat = k;
+      s->status |= OR_PROBE_SATURATED;
+      stopped = 1;
+    } else {
+      s->B = 2 * B;
+    }
+  }
+  if (!stopped) {
+    s->k_prev = k;
+    s->B_star = B;
+    s->khat = k;
+    if (s->iter >= p->P_max) {
+      s->status |= OR_PROBE_NOT_CONVERGED;
+      stopped = 1;
+    }
+  }
+  if (stopped) {
+    s->done = 1;
+    if (s->khat <= 0) s->status |= OR_EMPTY;
+  }
+  return dec;
+}
+
 void or_default_params(or_params *p, int ndim, int64_t n) {
   memset(p, 0, sizeof(*p));
   p->ndim = ndim;
@@ -788,64 +867,30 @@ int or_atsfft(const or_params *p, const double *x, or_result *r) {
     B_star = p->fixed_B;
     khat = p->fixed_k;
   } else {
-    int64_t B = p->B0, k_prev = 0;
-    uint64_t visited = 0;
-    int stopped = 0;
-    for (int i = 0; i < p->P_max; i++) {
+    or_probe_state ps;
+    or_probe_init(p, &ps);
+    while (!ps.done) {
+      int64_t B = ps.B;
+      int i = ps.iter;
       int64_t cnt = bcount(nd, B);
       hash_loop(p, x, OR_PHASE_PROBE, i, B, p->alpha_probe, yh, sig, tau, sinv);
       for (int64_t b = 0; b < cnt; b++) m[b] = yh[2 * b] * yh[2 * b] + yh[2 * b + 1] * yh[2 * b + 1];
       double T = or_threshold(m, cnt, p->q, p->noise_rate, p->rho);
       int64_t k = nd == 1 ? or_local_max_1d(m, B, T) : or_local_max_2d(m, B, T);
-      int lgB = 0;
-      while (((int64_t)1 << lgB) < B) lgB++;
-      visited |= (uint64_t)1 << lgB;
-      int dec = (i == 0) ? 1 : or_rule(k_prev, k);
-      /* occupancy guard: while fewer than gamma buckets per counted maximum
-         exist, merged neighbours bias the count and the ratio means nothing */
-      if (p->gamma > 0 && cnt < (int64_t)p->gamma * k) dec = 1;
       r->probe_B[i] = B;
       r->probe_k[i] = k;
       r->probe_T[i] = T;
-      r->probe_decision[i] = dec;
-      r->n_probe = i + 1;
-      if (dec == 0) {
-        B_star = B;
-        khat = k;
-        stopped = 1;
-      } else if (dec < 0) {
-        if (B / 2 < p->B0 || (p->gamma > 0 && bcount(nd, B / 2) < (int64_t)p->gamma * k)) {
-          B_star = B;
-          khat = k;
-          stopped = 1;
-        } else if (visited & ((uint64_t)1 << (lgB - 1))) {
-          B_star = B / 2;
-          khat = k;
-          stopped = 1;
-        } else {
-          B = B / 2;
-        }
-      } else {
-        if (2 * B > p->B_max) {
-          B_star = B;
-          khat = k;
-          r->status |= OR_PROBE_SATURATED;
-          stopped = 1;
-        } else {
-          B = 2 * B;
-        }
-      }
-      if (stopped) break;
-      k_prev = k;
-      B_star = r->probe_B[i];
-      khat = k;
+      r->probe_decision[i] = or_probe_step(p, &ps, k);
+      r->n_probe = ps.iter;
     }
-    if (!stopped) r->status |= OR_PROBE_NOT_CONVERGED;
+    B_star = ps.B_star;
+    khat = ps.khat;
+    r->status |= ps.status;
   }
   r->B_star = B_star;
   r->khat = khat;
   if (khat <= 0) {
-    r->status |= OR_EMPTY;
+    r->status |= OR_EMPTY; /* the probe's outcome, or fixed_k = 0 */
     free(yh);
     free(m);
     return 0;

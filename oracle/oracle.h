@@ -129,6 +129,26 @@ double or_median(const double *v, int L);
 double or_l1_error(int64_t total, const double *Xtrue, int64_t count, const int64_t *locs,
                    const double *vals, int64_t k);
 
+/* State of the adaptive-B probe (Sec. III-A, Algorithm 2) between its
+   iterations.  or_probe_init starts it at B0; or_probe_step takes the
+   local-maximum count k of the iteration just hashed at s->B and applies the
+   B-update rule, the occupancy guard and the stop rules, returning the
+   decision (-1 halve, 0 keep, +1 double).  Once s->done is set, B_star, khat
+   and status (OR_PROBE_SATURATED, OR_PROBE_NOT_CONVERGED, OR_EMPTY) hold the
+   probe's outcome. */
+typedef struct {
+  int64_t B;        /* bucket count (per axis) of the next iteration */
+  int64_t k_prev;   /* the previous iteration's count */
+  uint64_t visited; /* bit log2(B) set once B was hashed */
+  int iter;         /* iterations run */
+  int done;
+  int status;
+  int64_t B_star, khat;
+} or_probe_state;
+
+void or_probe_init(const or_params *p, or_probe_state *s);
+int or_probe_step(const or_params *p, or_probe_state *s, int64_t k);
+
 void or_default_params(or_params *p, int ndim, int64_t n);
 int or_atsfft(const or_params *p, const double *x, or_result *r);
 

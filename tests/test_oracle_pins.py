@@ -410,3 +410,40 @@ def test_probe_is_a_doubling_chain(orc):
                 B = r["probe_B"]
                 assert all(B[i + 1] == 2 * B[i] for i in range(len(B) - 1)), (ndim, n, k, seed, gamma, B)
                 assert all(d == 1 for d in r["probe_decision"][:-1])
+
+
+def test_probe_stop_table(orc):
+    """The probe's stop logic against a hand-derived decision table: keep,
+    halving into a hashed B (khat from the larger B), the halve floor at the
+    occupancy guard, the guard's exact boundaries, saturation, P_max, runs of
+    zero counts and EMPTY, gamma = 0, and 2D."""
+    for row in _golden_rows("probe_stop_table.txt"):
+        ndim, B0, B_max, P_max, gamma = (int(v) for v in row[:5])
+        counts = [int(v) for v in row[5].split(",")]
+        decs = [int(v) for v in row[6].split(",")]
+        B_star, khat, status = (int(v) for v in row[7:10])
+        n = 1 << 22 if ndim == 1 else 1 << 10
+        p = orc.Params.defaults(ndim, n, B0=B0, B_max=B_max, P_max=P_max, gamma=gamma)
+        r = orc.probe_run(p, lambda B: counts[(B // B0).bit_length() - 1])
+        assert r["probe_decision"] == decs, (row, r)
+        assert r["probe_B"] == [B0 << j for j in range(len(decs))], (row, r)
+        assert (r["B_star"], r["khat"], r["status"]) == (B_star, khat, status), (row, r)
+
+
+def test_atsfft_probe_follows_the_step_function(orc):
+    """or_atsfft's probe trace, replayed through the step function with its own
+    counts, gives the same decisions and outcome (the full run and the pinned
+    state machine are one and the same)."""
+    for ndim, n, k, snr in ((1, 1 << 14, 8, None), (1, 1 << 16, 40, 30.0), (2, 256, 6, None)):
+        gen = synth.planted_1d if ndim == 1 else synth.planted_2d
+        for seed in range(3):
+            x = gen(n, k, seed, snr_db=snr)[0]
+            kw = dict(alpha=8, alpha_probe=4, B_max=32) if ndim == 2 else {}
+            for gamma in (32, 0):
+                p = orc.Params.defaults(ndim, n, seed=seed, gamma=gamma, **kw)
+                r = orc.atsfft(x, p, trace=False)
+                by_B = dict(zip(r["probe_B"], r["probe_k"]))
+                s = orc.probe_run(p, by_B)
+                assert s["probe_decision"] == r["probe_decision"]
+                assert (s["B_star"], s["khat"]) == (r["B_star"], r["khat"])
+                assert s["status"] == r["status"] & ~orc.TRUNCATED
