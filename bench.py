@@ -152,20 +152,58 @@ def touched_bytes(desc, trs):
     return main, step
 
 
-def cpu_baseline(desc, xs, budget_s):
-    """The FP64 oracle, single-threaded, on the first signals of the batch."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(desc, xs, budget_s, min_signals=8):
+    """The FP64 oracle, single-threaded, on the first signals of the batch
+    (at least min_signals, then until the time budget is spent).  Returns the
+    baseline record and the oracle's results, signal by signal."""
     import oracle
 
-    done, t0 = 0, time.perf_counter()
+    done, t0, results = 0, time.perf_counter(), []
     while done < len(xs):
-        oracle.atsfft(xs[done].astype(np.complex128), oracle_params(desc, done), trace=False)
+        results.append(oracle.atsfft(xs[done].astype(np.complex128), oracle_params(desc, done), trace=False))
         done += 1
         log(f"cpu baseline: {done} transform(s), {time.perf_counter() - t0:.1f} s")
-        if time.perf_counter() - t0 >= budget_s:
+        if done >= min_signals and time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "transforms/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} full-size transforms (n=2^22, c64 input upcast to FP64), one thread, {el:.1f} s"}
+    rec = {"value": done / el, "unit": "transforms/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} full-size transforms (n=2^22, c64 input upcast to FP64), one thread, {el:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    return rec, results
+
+
+def oracle_agreement(res, refs):
+    """GPU results against the oracle's on the same signals: the located sets'
+    symmetric difference (summed and per signal) and the largest relative value
+    error, with the denominator max(|X_oracle(f)|, 1e-3 max_g |X_oracle(g)|) on
+    the frequencies both located."""
+    diffs, errs = [], []
+    for r, o in zip(res, refs):
+        diffs.append(int(np.setxor1d(r["locs"], o["locs"]).size))
+        common, ig, io = np.intersect1d(r["locs"], o["locs"], return_indices=True)
+        if common.size:
+            ref = o["vals"][io]
+            den = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(o["vals"])))
+            errs.append(float(np.max(np.abs(r["vals"][ig] - ref) / den)))
+        else:
+            errs.append(0.0)
+    return {"oracle_signals": len(refs), "oracle_set_diff": int(sum(diffs)),
+            "oracle_set_diff_per_signal": diffs, "oracle_max_rel_err": max(errs) if errs else None,
+            "oracle_mean_rel_err": float(np.mean(errs)) if errs else None}
 
 
 def _oracle_uneven_one(job):
@@ -406,10 +444,11 @@ def main():
     if args.copy_calibration:
         copy_calibration()
 
-    cpu = None
+    cpu, agree = None, {}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(d, xh, args.cpu_seconds)
+        cpu, refs = cpu_baseline(d, xh, args.cpu_seconds)
+        agree = oracle_agreement(res[:len(refs)], refs)
 
     line = {
         "metric": METRIC,
@@ -436,6 +475,7 @@ def main():
         "touched_bytes_per_step": touched_step,
         "touched_frac_of_step": touched_step / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
+        **agree,
         "dense_fft_ms_per_transform": ms_dense / batch,
         "atsfft_ms_per_transform": ms_step / batch,
         "speedup_vs_dense_fft": ms_dense / ms_step,

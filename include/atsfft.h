@@ -58,7 +58,11 @@ enum {
   ATSFFT_SIG_PROBE_NOT_CONVERGED = 2, /* the probe hit its iteration limit */
   ATSFFT_SIG_PROBE_SATURATED = 4,     /* the probe wanted a bucket count above B_max */
   ATSFFT_SIG_EMPTY = 8,               /* the probed sparsity is 0: nothing located */
-  ATSFFT_SIG_RETRIED = 16             /* the residual test re-ran location at a larger B */
+  ATSFFT_SIG_RETRIED = 16,            /* the residual test re-ran location at a larger B */
+  ATSFFT_SIG_PROBE_TIMEOUT = 32       /* a probe level's count never reached the probe control
+                                         within its bounded wait: the probe stopped at the last
+                                         level it acted on (B_star, khat as that level left them;
+                                         EMPTY if none), so B_star and khat are not the method's */
 };
 
 /* Descriptor flags. */
@@ -195,6 +199,11 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  *   ATSFFT_STREAM_ROWS   rows per workgroup of the streamed 2D hash, 1..64 (2)
  *   ATSFFT_GATHER_LDS    0: the adjoint gather reads bucket adjoints from
  *                        device memory instead of staging them in LDS
+ *   ATSFFT_PROBE_SPIN    sleeps (s_sleep 2 each) the probe control waits for
+ *                        a level's count still in flight before it gives up
+ *                        with ATSFFT_SIG_PROBE_TIMEOUT, 0..2^24 (2^20)
+ *   ATSFFT_PROBE_DROP_LEVEL  test hook: the probe level whose count is never
+ *                        recorded, so that the wait gives up (unset: none)
  */
 atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d);
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libatsfft.so")
 SUCCESS, EINVAL, ENODEVICE, ENOMEM, ELAUNCH, ENOTSUPPORTED = range(6)
 C64, C128 = 0, 1
 SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY, SIG_RETRIED = 0, 1, 2, 4, 8, 16
+SIG_PROBE_TIMEOUT = 32
 FLAG_FIXED_B = 1
 FLAG_PROFILE = 2
 FLAG_COMPENSATED = 4

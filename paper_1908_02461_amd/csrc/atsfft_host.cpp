@@ -34,6 +34,8 @@ struct atsfft_plan_s {
   uint32_t gather_lds;  // adjoint gather: most LDS bytes for a staged bucket adjoint (0: none)
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
+  uint32_t probe_spin;  // sleeps before the probe control gives up waiting for a count
+  int32_t probe_drop;   // test hook: probe level whose count is never recorded (-1: none)
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
   // uneven batches: one plan per power-of-two length below n (index log2 n'),
@@ -285,6 +287,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.gather_lds = plan->gather_lds;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
+  P.probe_spin = plan->probe_spin;
+  P.probe_drop = plan->probe_drop;
   P.tile_slots = plan->tile_slots;
   P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
@@ -458,6 +462,16 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   if (const char *env = std::getenv("ATSFFT_PROBE_STEP")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 32) p->probe_step = (uint32_t)v;
+  }
+  p->probe_spin = 1u << 20;
+  if (const char *env = std::getenv("ATSFFT_PROBE_SPIN")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 0 && v <= (1L << 24)) p->probe_spin = (uint32_t)v;
+  }
+  p->probe_drop = -1;
+  if (const char *env = std::getenv("ATSFFT_PROBE_DROP_LEVEL")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 0 && v < kMaxProbe) p->probe_drop = (int32_t)v;
   }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
   p->bwd_smem = bwd_smem_bytes(d->dtype, p->Bc_max, (uint32_t)d->max_out);

@@ -30,6 +30,7 @@ enum : uint32_t {
   kSigSaturated = 4,
   kSigEmpty = 8,
   kSigRetried = 16,
+  kSigProbeTimeout = 32,
 };
 
 enum : int { kPhaseProbe = 0, kPhaseLoc = 1, kPhaseEst = 2 };
@@ -86,6 +87,8 @@ struct KParams {
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
+  uint32_t probe_spin;   // sleeps before the probe control stops waiting for a level's count
+  int32_t probe_drop;    // test hook: probe level whose count is never recorded (-1: none)
   uint64_t probe_off[kMaxProbe];       // complex offset of level i's bucket arrays in the probe area
   double q, neg_log1mq, noise_rate, rho;
   double res_tol;        // residual test: re-run at 2 B_star above this E_res / E_tot (0: off)

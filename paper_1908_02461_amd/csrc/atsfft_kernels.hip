@@ -999,11 +999,19 @@ __device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
     // every workgroup of the round stored its count before it counted itself
     // in; a store still on its way reads as -1 (k_init's value) for a while
     int k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int spin = 0; k < 0 && spin < (1 << 20); ++spin) {
+    for (uint32_t spin = 0; k < 0 && spin < P.probe_spin; ++spin) {
       __builtin_amdgcn_s_sleep(2);
       k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (k < 0) k = 0;
+    if (k < 0) {
+      // the count never arrived: the probe stops at the last level it acted
+      // on (B_star and khat as that level left them; before level 0, B0 and
+      // khat = 0, so EMPTY) and the signal carries PROBE_TIMEOUT
+      s.status |= kSigProbeTimeout;
+      s.done = 1;
+      if (s.khat <= 0) s.status |= kSigEmpty;
+      break;
+    }
     int dec = i == 0 ? 1 : brule(s.k_prev, k);
     if (P.gamma > 0 && Bc < (long long)P.gamma * (long long)k) dec = 1;
     s.visited |= 1u << logB;
@@ -1285,7 +1293,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
       h->B = (int32_t)B;
       h->dec = 0;
       h->T = Td;
-      __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((int32_t)level != P.probe_drop)
+        __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // the last of the round's workgroups of this signal applies the rule;
       // it reads only the counts, themselves atomics, so no fence (an
       // agent-scope fence writes back and invalidates the L2)

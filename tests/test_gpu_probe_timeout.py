@@ -1,0 +1,64 @@
+"""The probe control's bounded wait for a level's count (the counts of a
+round's levels reach the last workgroup through device-scope atomics) gives
+up visibly: a test hook keeps one level's count from ever being recorded and
+a short spin limit ends the wait.  Every kernel still exits normally; the
+signal carries ATSFFT_SIG_PROBE_TIMEOUT and stops at the last level the
+probe acted on, and its location and estimation are then those of the
+oracle's fixed-B form (Algorithm 1) at that B and khat."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02461_amd import synth
+
+from parity_util import oracle_params, run_gpu, value_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_02461_amd import atsfft
+
+    atsfft.load()
+    return atsfft
+
+
+def test_dropped_probe_count_sets_timeout(A, monkeypatch):
+    n, k = 1 << 14, 8
+    xs = np.stack([synth.planted_1d(n, k, 300 + i)[0] for i in range(2)])
+    plain = A.Plan(1, n, "c128", seed=4, max_batch=2)
+    out0 = run_gpu(plain, xs)
+    tr0 = [plain.trace(out0["ws"], i, full=False) for i in range(2)]
+    for i in range(2):
+        assert not plain.results(out0, i)["status"] & A.SIG_PROBE_TIMEOUT
+        # the occupancy guard doubles up to B = 256 at k = 8: level 2 is reached
+        assert tr0[i]["n_probe"] > 2, tr0[i]
+    for drop in (2, 0):
+        monkeypatch.setenv("ATSFFT_PROBE_DROP_LEVEL", str(drop))
+        monkeypatch.setenv("ATSFFT_PROBE_SPIN", "64")
+        plan = A.Plan(1, n, "c128", seed=4, max_batch=2)
+        monkeypatch.delenv("ATSFFT_PROBE_DROP_LEVEL")
+        monkeypatch.delenv("ATSFFT_PROBE_SPIN")
+        print(f"probe timeout: dropped level {drop}", flush=True)
+        out = run_gpu(plan, xs)
+        for i in range(2):
+            res = plan.results(out, i)
+            tr = plan.trace(out["ws"], i, full=False)
+            assert res["status"] & A.SIG_PROBE_TIMEOUT, (drop, i, res["status"])
+            assert tr["n_probe"] == drop
+            assert tr["probe_k"] == tr0[i]["probe_k"][:drop]
+            if drop == 0:
+                assert res["status"] & A.SIG_EMPTY and res["count"] == 0
+                continue
+            B = 32 << (drop - 1)
+            assert (tr["B_star"], res["khat"]) == (B, tr0[i]["probe_k"][drop - 1])
+            p = oracle_params(plan, i)
+            p.fixed_B, p.fixed_k = B, res["khat"]
+            ref = oracle.atsfft(xs[i], p, trace=False)
+            assert np.array_equal(res["locs"], ref["locs"]), (drop, i)
+            assert value_rel_err(res["vals"], ref["vals"]) < 1e-10
