@@ -252,6 +252,30 @@ atsfft_status atsfft_execute_uneven(atsfft_plan_t plan, int32_t batch, const voi
 /* Workspace bytes of atsfft_execute_uneven for the lengths ns (host, [batch]). */
 atsfft_status atsfft_workspace_size_uneven(atsfft_plan_t plan, int32_t batch, const int64_t *ns, size_t *bytes);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * atsfft_execute_batched with its workspace in a fixed device array that the
+ * library holds on each device it runs on, ATSFFT_NOALLOC_WORKSPACE_BYTES
+ * (64 MiB) per device, kept until the process ends.  The call allocates
+ * nothing (no hipMalloc, pinned memory, event or graph); the caller passes
+ * the input and the outputs exactly as for atsfft_execute_batched and gets
+ * the same results.  Every call on one device shares that device's array:
+ * calls that overlap on one device (other streams, other threads, other
+ * plans) race and give undefined results, and atsfft_trace_read and
+ * atsfft_backward do not apply (the workspace is not the caller's).  The
+ * array keeps the previous call's contents; the call needs no particular
+ * contents on entry.
+ * Errors: ATSFFT_EINVAL (a plan with ATSFFT_FLAG_GRAPH or ATSFFT_FLAG_PROFILE,
+ * which allocate; batch outside [1, max_batch]; a null pointer; a batch whose
+ * atsfft_workspace_size exceeds ATSFFT_NOALLOC_WORKSPACE_BYTES, with the
+ * sizes in atsfft_last_error), ATSFFT_ELAUNCH.
+ */
+#define ATSFFT_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+atsfft_status atsfft_execute_batched_noalloc(atsfft_plan_t plan, int32_t batch, const void *x_dev,
+                                             int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
+                                             int32_t *khat_dev, uint32_t *sig_status_dev, hipStream_t stream);
+
 /* atsfft_execute_batched with batch = 1. */
 atsfft_status atsfft_execute(atsfft_plan_t plan, const void *x_dev, int64_t *locs_dev,
                              void *vals_dev, int32_t *count_dev, int32_t *khat_dev,

@@ -85,8 +85,9 @@ EXPORTS = (
     "atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
     "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
     "atsfft_status_string", "atsfft_version", "atsfft_last_error", "atsfft_profile_read",
-    "atsfft_execute_uneven", "atsfft_workspace_size_uneven",
+    "atsfft_execute_uneven", "atsfft_workspace_size_uneven", "atsfft_execute_batched_noalloc",
 )
+NOALLOC_WORKSPACE_BYTES = 64 << 20  # ATSFFT_NOALLOC_WORKSPACE_BYTES
 
 _lib = None
 
@@ -114,6 +115,7 @@ def load():
     L.atsfft_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(sz)]
     L.atsfft_execute_batched.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.atsfft_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.atsfft_execute_batched_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp]
     L.atsfft_backward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.atsfft_trace_read.argtypes = [vp, vp, C.c_int32, C.POINTER(Trace), vp]
     L.atsfft_destroy.argtypes = [vp]
@@ -127,7 +129,8 @@ def load():
     L.atsfft_last_error.restype = C.c_char_p
     for name in ("atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
                  "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
-                 "atsfft_profile_read", "atsfft_execute_uneven", "atsfft_workspace_size_uneven"):
+                 "atsfft_profile_read", "atsfft_execute_uneven", "atsfft_workspace_size_uneven",
+                 "atsfft_execute_batched_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -237,6 +240,25 @@ class Plan:
             out["count"].data_ptr(), out["khat"].data_ptr(), out["status"].data_ptr(), ws.data_ptr(),
             ws.numel(), s), "atsfft_execute_batched")
         out["ws"] = ws
+        return out
+
+    def execute_noalloc(self, x, out: dict, stream=None) -> dict:
+        """atsfft_execute_batched_noalloc: the batched execute with the
+        library's fixed device workspace; out (from outputs()) is required so
+        that the call itself allocates nothing."""
+        import torch
+
+        if not x.is_cuda or x.dtype != self.torch_dtype or not x.is_contiguous():
+            raise ValueError("x must be a contiguous device tensor of the plan's complex dtype")
+        shape = (self.n,) if self.ndim == 1 else (self.n, self.n)
+        if tuple(x.shape[1:]) != shape:
+            raise ValueError(f"x must have shape [batch, {', '.join(map(str, shape))}]")
+        batch = x.shape[0]
+        s = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+        _check(load().atsfft_execute_batched_noalloc(
+            self._h, batch, x.data_ptr(), out["locs"].data_ptr(), out["vals"].data_ptr(),
+            out["count"].data_ptr(), out["khat"].data_ptr(), out["status"].data_ptr(), s),
+            "atsfft_execute_batched_noalloc")
         return out
 
     def execute_uneven(self, x, offsets, ns, out: Optional[dict] = None, ws=None, stream=None) -> dict:

@@ -54,7 +54,13 @@ struct atsfft_plan_s {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream;
+  // the device's fixed workspace (atsfft_execute_batched_noalloc), or null
+  // when its address lookup failed (scratch_err)
+  void *scratch;
+  hipError_t scratch_err;
 };
+
+static_assert(kScratchBytes == ATSFFT_NOALLOC_WORKSPACE_BYTES, "fixed workspace size and its header constant");
 
 namespace {
 
@@ -562,6 +568,14 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     free_plan(p);
     return fail(ATSFFT_ELAUNCH, "window table upload or kernel setup failed");
   }
+  // the fixed workspace's device address, looked up once per device (the
+  // plan's device is current here); only atsfft_execute_batched_noalloc uses it
+  p->scratch = nullptr;
+  p->scratch_err = scratch_address(p->device, &p->scratch);
+  if (p->scratch_err != hipSuccess) {
+    p->scratch = nullptr;
+    (void)hipGetLastError();
+  }
   *out = p;
   return ATSFFT_SUCCESS;
 }
@@ -680,6 +694,35 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
       (void)hipEventRecord((*m->rec)[(size_t)stage], m->s);
     };
   if (launch_execute(P, d.dtype, batch, stream, mark, &mctx) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_execute_batched_noalloc(atsfft_plan_t plan, int32_t batch, const void *x_dev,
+                                             int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
+                                             int32_t *khat_dev, uint32_t *sig_status_dev, hipStream_t stream) {
+  if (!plan) return fail(ATSFFT_EINVAL, "null plan");
+  if (plan->d.flags & (ATSFFT_FLAG_GRAPH | ATSFFT_FLAG_PROFILE))
+    return fail(ATSFFT_EINVAL, "the fixed-workspace execute takes no GRAPH or PROFILE plan (both allocate)");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  if (!x_dev || !locs_dev || !vals_dev || !count_dev || !khat_dev || !sig_status_dev)
+    return fail(ATSFFT_EINVAL, "null device pointer");
+  const Layout lay = make_layout(plan, batch);
+  if (lay.total > kScratchBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "batch %d needs %zu bytes of workspace, above the fixed workspace of %zu bytes "
+                  "(ATSFFT_NOALLOC_WORKSPACE_BYTES)",
+                  (int)batch, lay.total, kScratchBytes);
+    return fail(ATSFFT_EINVAL, msg);
+  }
+  if (!plan->scratch)
+    return fail(ATSFFT_ELAUNCH, std::string("fixed workspace address lookup failed: ") +
+                                    hipGetErrorString(plan->scratch_err));
+  KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, plan->scratch);
+  if (launch_execute(P, plan->d.dtype, batch, stream, nullptr, nullptr) != hipSuccess) {
     hipError_t e = hipGetLastError();
     return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   }

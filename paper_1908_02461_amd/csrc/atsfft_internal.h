@@ -23,6 +23,9 @@ constexpr size_t kGatherLdsBytes = 65536;  // adjoint gather: most LDS for a sta
 constexpr int kRowTaps = 8;                // 2D row hash: column wraps per thread, at most
 constexpr uint32_t kRowBytes = 64u << 10;  // 2D row hash: largest row staged in LDS
 constexpr int kMaxOut = 16384;
+// fixed device workspace of atsfft_execute_batched_noalloc (bytes per device)
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
 
 enum : uint32_t {
   kSigTruncated = 1,
@@ -130,5 +133,8 @@ size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
 size_t estimate_smem_bytes(uint32_t max_out);
 size_t residual_smem_bytes(int dtype, uint32_t Bc_max);
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);
+// Device address of `device`'s fixed workspace (kScratchBytes), looked up once
+// per device; `device` must be the current device on the first call for it.
+hipError_t scratch_address(int device, void **ptr);
 
 }  // namespace atsfft

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "atsfft_internal.h"
 
@@ -2265,6 +2266,30 @@ hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c
   const int64_t blocks = (c + 1 + threads - 1) / threads;
   hipLaunchKernelGGL(k_window_hat, dim3((uint32_t)blocks), dim3(threads), 0, s, taps, w, n, c, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ fixed workspace ----
+
+// The workspace of atsfft_execute_batched_noalloc, for callers that cannot
+// allocate device memory.  Each device the library runs on holds its own copy
+// until the process ends.  In host code the array's name is only a host-side
+// stand-in, never a device address: scratch_address looks the address up once
+// per device with hipGetSymbolAddress, and host code uses that address alone.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **ptr) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (!ptr || device < 0 || device >= kMaxDevices) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------ launches ----
