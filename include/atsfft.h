@@ -188,7 +188,7 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  * Launch-shape settings, read from the environment when a plan is created
  * (for measurement; the defaults are the measured best on gfx950, and none of
  * them changes a result beyond the order of floating-point sums):
- *   ATSFFT_HASH_LOOPS    1D main loops per hash workgroup, 1..3 (1)
+ *   ATSFFT_HASH_LOOPS    1D main loops per hash workgroup, 1..3 (3)
  *   ATSFFT_TILE_SLOTS    hash workgroups per slab and loop, 1..64 (32)
  *   ATSFFT_VOTE_BLOCKS   vote workgroups per candidate loop (128 / batch, >= 32;
  *                        2D: 256 / batch, >= 64)
@@ -199,6 +199,8 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  *   ATSFFT_STREAM_ROWS   rows per workgroup of the streamed 2D hash, 1..64 (2)
  *   ATSFFT_GATHER_LDS    0: the adjoint gather reads bucket adjoints from
  *                        device memory instead of staging them in LDS
+ *   ATSFFT_GATHER_BLOCKS adjoint gather workgroups per signal, 1..1024
+ *                        (1024); the rest of a signal by grid stride
  *   ATSFFT_PROBE_SPIN    sleeps (s_sleep 2 each) the probe control waits for
  *                        a level's count still in flight before it gives up
  *                        with ATSFFT_SIG_PROBE_TIMEOUT, 0..2^24 (2^20)

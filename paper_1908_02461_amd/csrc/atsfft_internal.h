@@ -87,6 +87,7 @@ struct KParams {
   uint32_t rows2d;       // the form this launch sequence uses (0, 1 or 2)
   uint32_t stream_rows;  // streamed form: rows per workgroup
   uint32_t gather_lds;   // adjoint gather: most LDS bytes for a staged bucket adjoint (0: none)
+  uint32_t gather_blocks;  // adjoint gather: most workgroups per signal (the rest by grid stride)
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels

@@ -325,10 +325,13 @@ __global__ void k_init(KParams P, int batch) {
 // (kSlabs x kTileSlots, loops, signals) and is dispatched signal by signal,
 // so the resident workgroups cover about one signal at a time.
 //
-// A workgroup owns 64-bucket tiles (slot, slot + kTileSlots, ...); its four
-// 64-lane groups split each bucket's w/B wraps and issue their in-slab loads
-// eight wraps at a time; a fixed-order LDS sum combines the groups into the
-// slab's partial y_b.  k_bucket adds the kSlabs partials in slab order.
+// A workgroup owns 64-bucket tiles (slot, slot + kTileSlots, ...) of up to
+// three loops (1D main pass); its four 64-lane groups split each bucket's w/B
+// wraps and issue their in-slab loads eight wraps at a time; a wrap's window
+// tap depends only on the bucket and the wrap, so every lane loads it once
+// (coalesced) for all the workgroup's loops; a fixed-order LDS sum combines
+// the groups into the slab's partial y_b.  k_bucket adds the kSlabs partials
+// in slab order.
 constexpr int kTile = 64;        // buckets per tile
 constexpr int kVoteIlp = 4;      // vote candidates tested together
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
@@ -429,7 +432,11 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
         }
         for (uint32_t r0 = g; r0 < wraps; r0 += 4 * kHashU) {
           C v[LG][kHashU];
-          R gt[LG][kHashU];
+          R gt[kHashU];
+          // a wrap's tap is the same for every loop: one load by every lane
+          // (64 consecutive taps, two lines), shared by the workgroup's loops
+#pragma unroll
+          for (int u = 0; u < kHashU; ++u) gt[u] = r0 + 4u * u < wraps ? G[b + ((r0 + 4u * u) << logB)] : (R)0;
 #pragma unroll
           for (int q = 0; q < LG; ++q) {
 #pragma unroll
@@ -439,11 +446,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
               a[q] = (aq + step[q]) & mask;
               v[q][u].x = 0;
               v[q][u].y = 0;
-              gt[q][u] = 0;
-              if (pp) {
-                v[q][u] = x[aq];
-                gt[q][u] = G[b + ((r0 + 4u * u) << logB)];
-              }
+              if (pp) v[q][u] = x[aq];
             }
           }
 #pragma unroll
@@ -451,11 +454,11 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
 #pragma unroll
             for (int u = 0; u < kHashU; ++u) {
               if constexpr (COMP) {
-                neumaier_fma(ax[q], cx[q], v[q][u].x, gt[q][u]);
-                neumaier_fma(ay[q], cy[q], v[q][u].y, gt[q][u]);
+                neumaier_fma(ax[q], cx[q], v[q][u].x, gt[u]);
+                neumaier_fma(ay[q], cy[q], v[q][u].y, gt[u]);
               } else {
-                ax[q] += v[q][u].x * gt[q][u];
-                ay[q] += v[q][u].y * gt[q][u];
+                ax[q] += v[q][u].x * gt[u];
+                ay[q] += v[q][u].y * gt[u];
               }
             }
           }
@@ -2210,7 +2213,7 @@ static hipError_t run_backward(const KParams &P, int batch, const void *grad_val
   const size_t smem = bwd_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max, P.max_out);
   hipLaunchKernelGGL((k_bwd_bucket<R, NDIM>), dim3(P.L_est, batch), dim3(kBucketThreads), smem, s, P, grad_vals);
   const uint32_t span = kGatherThreads * gather_per<R, NDIM>();
-  const uint32_t blocks = (uint32_t)std::min<int64_t>((P.x_sig + span - 1) / span, 1024);
+  const uint32_t blocks = (uint32_t)std::min<int64_t>((P.x_sig + span - 1) / span, (int64_t)P.gather_blocks);
   const size_t lds = std::min<size_t>((size_t)P.Bc_max * 2 * sizeof(R), P.gather_lds);
   hipLaunchKernelGGL((k_bwd_gather<R, NDIM>), dim3(blocks, batch), dim3(kGatherThreads), lds, s, P, grad_x,
                      (uint32_t)lds);
