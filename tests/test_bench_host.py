@@ -22,8 +22,10 @@ def test_oracle_agreement_uses_the_floor_denominator():
     # a near-zero oracle value is measured against 1e-3 of the largest one
     refs = [dict(locs=np.array([0, 1]), vals=np.array([1e-9 + 0j, 10.0 + 0j]))]
     res = [dict(locs=np.array([0, 1]), vals=np.array([1e-3 + 0j, 10.0 + 0j]))]
-    a = bench.oracle_agreement(res, refs)
+    a = bench.oracle_agreement(res, refs, floor=1e-3)
     assert abs(a["oracle_max_rel_err"] - (1e-3 - 1e-9) / 1e-2) < 1e-9
+    a = bench.oracle_agreement(res, refs)  # FP32 floor: 1e-2 of the largest
+    assert abs(a["oracle_max_rel_err"] - (1e-3 - 1e-9) / 1e-1) < 1e-9
 
 
 def test_cpu_model_is_named():

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_1908_02461_amd import synth
 
-from parity_util import VAL_TOL, value_rel_err
+from parity_util import VAL_TOL, sub_params, value_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -22,18 +22,6 @@ def A():
 
     atsfft.load()
     return atsfft
-
-
-def _sub_params(d, m, signal):
-    """The oracle knobs of the plan's table for length m (B0 and B_max clipped
-    to m as the library documents)."""
-    B_max = min(d.B_max, max(m // d.alpha, 1))
-    B_max = max(B_max, 2 if d.ndim == 1 else 4)
-    B0 = min(d.B0, B_max)
-    return oracle.Params(
-        ndim=d.ndim, n=m, B0=B0, B_max=B_max, alpha_probe=d.alpha_probe, alpha=d.alpha, L_loc=d.L_loc,
-        L_est=d.L_est, T_vote=d.T_vote, P_max=d.P_max, d=d.d, gamma=d.gamma, delta=d.delta, q=d.q,
-        noise_rate=d.noise_rate, rho=d.rho, seed=d.seed, signal=signal, max_out=d.max_out)
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
@@ -59,11 +47,11 @@ def test_uneven_lengths_match_oracle(A, dt):
     torch.cuda.synchronize()
     for i, (x, m) in enumerate(zip(xs, ns)):
         res = plan.results(out, i)
-        ref = oracle.atsfft(x.astype(np.complex128), _sub_params(plan.desc, m, i), trace=False)
+        ref = oracle.atsfft(x.astype(np.complex128), sub_params(plan.desc, m, i), trace=False)
         assert res["status"] == ref["status"] and res["khat"] == ref["khat"], (i, res["status"], ref["status"])
         assert res["count"] == ref["count"], (i, res["count"], ref["count"])
         assert np.array_equal(res["locs"], ref["locs"]), i
-        assert value_rel_err(res["vals"], ref["vals"]) < VAL_TOL[dt], i
+        assert value_rel_err(res["vals"], ref["vals"], dt) < VAL_TOL[dt], i
 
 
 def test_uneven_rejects_uncovered_length(A):

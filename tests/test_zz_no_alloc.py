@@ -32,7 +32,7 @@ def _same(plan, out_ref, out_fix, batch, label):
         f = plan.results(out_fix, i)
         assert (f["count"], f["khat"], f["status"]) == (r["count"], r["khat"], r["status"]), (label, i)
         assert np.array_equal(f["locs"], r["locs"]), (label, i)
-        assert value_rel_err(f["vals"], r["vals"]) < VAL_TOL[plan.dtype], (label, i)
+        assert value_rel_err(f["vals"], r["vals"], plan.dtype) < VAL_TOL[plan.dtype], (label, i)
 
 
 def _signals(n, k, seeds, snr, dtype):
