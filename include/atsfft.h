@@ -59,10 +59,12 @@ enum {
   ATSFFT_SIG_PROBE_SATURATED = 4,     /* the probe wanted a bucket count above B_max */
   ATSFFT_SIG_EMPTY = 8,               /* the probed sparsity is 0: nothing located */
   ATSFFT_SIG_RETRIED = 16,            /* the residual test re-ran location at a larger B */
-  ATSFFT_SIG_PROBE_TIMEOUT = 32       /* a probe level's count never reached the probe control
+  ATSFFT_SIG_PROBE_TIMEOUT = 32,      /* a probe level's count never reached the probe control
                                          within its bounded wait: the probe stopped at the last
                                          level it acted on (B_star, khat as that level left them;
                                          EMPTY if none), so B_star and khat are not the method's */
+  ATSFFT_SIG_BAD_LENGTH = 64          /* atsfft_execute_uneven_dev: the signal's length is not a
+                                         power of two in [n_min, n]; nothing ran (also EMPTY) */
 };
 
 /* Descriptor flags. */
@@ -250,6 +252,33 @@ atsfft_status atsfft_execute_uneven(atsfft_plan_t plan, int32_t batch, const voi
                                     const int64_t *ns, int64_t *locs_dev, void *vals_dev, int32_t *count_dev,
                                     int32_t *khat_dev, uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes,
                                     hipStream_t stream);
+
+/*
+ * Algorithm 2 on an uneven 1D batch whose lengths and offsets are DEVICE
+ * arrays (int64 [batch]): signal i starts at complex element offsets_dev[i]
+ * of x_dev and has length ns_dev[i].  The host reads neither array, so the
+ * call is a fixed sequence of kernel launches whatever the lengths (no
+ * grouping on the host, no host-to-device copy) and can be captured into a
+ * HIP graph (ATSFFT_FLAG_GRAPH replays it; a caller may also capture it into
+ * its own graph); the arrays' contents may change between replays.  Every
+ * signal runs with the knobs and window tables of its own length, as in
+ * atsfft_execute_uneven, and draws with signal key i, so each signal's result
+ * equals that call's.  A length that is not a power of two in [n_min, n]
+ * gives ATSFFT_SIG_BAD_LENGTH | ATSFFT_SIG_EMPTY for that signal; offsets are
+ * the caller's to keep inside x_dev.  Needs a 1D plan with n_min > 0 and
+ * res_tol = 0; ws_dev must hold atsfft_workspace_size_uneven_dev(plan, batch)
+ * bytes.  The adjoint and the trace read do not apply.
+ * Errors: ATSFFT_EINVAL (a plan without this form, ATSFFT_FLAG_PROFILE, batch
+ * outside [1, max_batch], null pointers, workspace too small), ATSFFT_ELAUNCH.
+ */
+atsfft_status atsfft_execute_uneven_dev(atsfft_plan_t plan, int32_t batch, const void *x_dev,
+                                        const int64_t *offsets_dev, const int64_t *ns_dev, int64_t *locs_dev,
+                                        void *vals_dev, int32_t *count_dev, int32_t *khat_dev,
+                                        uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes of atsfft_execute_uneven_dev for `batch` signals: a slice of
+   the plan's longest length per signal, whatever the lengths. */
+atsfft_status atsfft_workspace_size_uneven_dev(atsfft_plan_t plan, int32_t batch, size_t *bytes);
 
 /* Workspace bytes of atsfft_execute_uneven for the lengths ns (host, [batch]). */
 atsfft_status atsfft_workspace_size_uneven(atsfft_plan_t plan, int32_t batch, const int64_t *ns, size_t *bytes);

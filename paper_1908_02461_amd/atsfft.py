@@ -20,6 +20,7 @@ SUCCESS, EINVAL, ENODEVICE, ENOMEM, ELAUNCH, ENOTSUPPORTED = range(6)
 C64, C128 = 0, 1
 SIG_OK, SIG_TRUNCATED, SIG_PROBE_NOT_CONVERGED, SIG_PROBE_SATURATED, SIG_EMPTY, SIG_RETRIED = 0, 1, 2, 4, 8, 16
 SIG_PROBE_TIMEOUT = 32
+SIG_BAD_LENGTH = 64
 FLAG_FIXED_B = 1
 FLAG_PROFILE = 2
 FLAG_COMPENSATED = 4
@@ -86,6 +87,7 @@ EXPORTS = (
     "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
     "atsfft_status_string", "atsfft_version", "atsfft_last_error", "atsfft_profile_read",
     "atsfft_execute_uneven", "atsfft_workspace_size_uneven", "atsfft_execute_batched_noalloc",
+    "atsfft_execute_uneven_dev", "atsfft_workspace_size_uneven_dev",
 )
 NOALLOC_WORKSPACE_BYTES = 64 << 20  # ATSFFT_NOALLOC_WORKSPACE_BYTES
 
@@ -123,6 +125,8 @@ def load():
     I64P = C.POINTER(C.c_int64)
     L.atsfft_execute_uneven.argtypes = [vp, C.c_int32, vp, I64P, I64P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.atsfft_workspace_size_uneven.argtypes = [vp, C.c_int32, I64P, C.POINTER(sz)]
+    L.atsfft_execute_uneven_dev.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.atsfft_workspace_size_uneven_dev.argtypes = [vp, C.c_int32, C.POINTER(sz)]
     L.atsfft_status_string.argtypes = [C.c_int]
     L.atsfft_status_string.restype = C.c_char_p
     L.atsfft_version.restype = C.c_char_p
@@ -130,7 +134,8 @@ def load():
     for name in ("atsfft_default_desc", "atsfft_plan", "atsfft_workspace_size", "atsfft_execute_batched",
                  "atsfft_execute", "atsfft_backward", "atsfft_trace_read", "atsfft_destroy",
                  "atsfft_profile_read", "atsfft_execute_uneven", "atsfft_workspace_size_uneven",
-                 "atsfft_execute_batched_noalloc"):
+                 "atsfft_execute_batched_noalloc", "atsfft_execute_uneven_dev",
+                 "atsfft_workspace_size_uneven_dev"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -288,6 +293,38 @@ class Plan:
             self._h, batch, x.data_ptr(), offs.ctypes.data_as(I64P), nsa.ctypes.data_as(I64P),
             out["locs"].data_ptr(), out["vals"].data_ptr(), out["count"].data_ptr(), out["khat"].data_ptr(),
             out["status"].data_ptr(), ws.data_ptr(), ws.numel(), s), "atsfft_execute_uneven")
+        out["ws"] = ws
+        return out
+
+    def workspace_size_uneven_dev(self, batch: int) -> int:
+        b = C.c_size_t()
+        _check(load().atsfft_workspace_size_uneven_dev(self._h, batch, C.byref(b)),
+               "atsfft_workspace_size_uneven_dev")
+        return int(b.value)
+
+    def execute_uneven_dev(self, x, offsets, ns, out: Optional[dict] = None, ws=None, stream=None) -> dict:
+        """Signals of different lengths packed in the 1D device tensor x, with
+        offsets and lengths given as int64 device tensors (the host reads
+        neither: the call can be captured into a graph)."""
+        import torch
+
+        if not x.is_cuda or x.dtype != self.torch_dtype or not x.is_contiguous():
+            raise ValueError("x must be a contiguous device tensor of the plan's complex dtype")
+        for t in (offsets, ns):
+            if not (t.is_cuda and t.dtype == torch.int64 and t.is_contiguous() and t.dim() == 1):
+                raise ValueError("offsets and ns must be contiguous 1D int64 device tensors")
+        batch = int(ns.numel())
+        if offsets.numel() != batch:
+            raise ValueError("offsets and ns must have the same length")
+        need = self.workspace_size_uneven_dev(batch)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+        out = out or self.outputs(batch, x.device)
+        s = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+        _check(load().atsfft_execute_uneven_dev(
+            self._h, batch, x.data_ptr(), offsets.data_ptr(), ns.data_ptr(), out["locs"].data_ptr(),
+            out["vals"].data_ptr(), out["count"].data_ptr(), out["khat"].data_ptr(), out["status"].data_ptr(),
+            ws.data_ptr(), ws.numel(), s), "atsfft_execute_uneven_dev")
         out["ws"] = ws
         return out
 

@@ -48,8 +48,9 @@ struct atsfft_plan_s {
   // ATSFFT_FLAG_GRAPH: the execute's launches captured once per call shape
   // (batch and buffers) on a plan-owned stream, replayed on the caller's
   struct GraphEntry {
+    int32_t kind;  // 0 batched execute, 1 uneven execute with device lengths
     int32_t batch;
-    const void *ptrs[7];
+    const void *ptrs[9];
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
@@ -59,6 +60,10 @@ struct atsfft_plan_s {
   // when its address lookup failed (scratch_err)
   void *scratch;
   hipError_t scratch_err;
+  // uneven batches with device-side lengths (1D, n_min > 0): the parameters
+  // of every covered length, log2 lengths dev_lg_lo..dev_lg_hi (device)
+  KParams *dev_tmpl;
+  uint32_t dev_lg_lo, dev_lg_hi;
 };
 
 static_assert(kScratchBytes == ATSFFT_NOALLOC_WORKSPACE_BYTES, "fixed workspace size and its header constant");
@@ -256,6 +261,7 @@ void free_plan(atsfft_plan_s *p) {
       for (hipEvent_t e : rec) (void)hipEventDestroy(e);
   if (p->G_dev) (void)hipFree(p->G_dev);
   if (p->Ghat_dev) (void)hipFree(p->Ghat_dev);
+  if (p->dev_tmpl) (void)hipFree(p->dev_tmpl);
   for (auto &g : p->graphs) {
     (void)hipGraphExecDestroy(g.exec);
     (void)hipGraphDestroy(g.graph);
@@ -324,6 +330,48 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.khat = khat_dev;
   P.status = sig_status_dev;
   return P;
+}
+
+// ATSFFT_FLAG_GRAPH: replay the launches `enqueue` makes for this call shape
+// (kind, batch and buffers), capturing them on the plan's own stream the
+// first time; the last kMaxGraphs shapes are kept.
+template <typename F>
+atsfft_status graph_launch(atsfft_plan_s *plan, int32_t kind, int32_t batch, const void *const key[9],
+                           hipStream_t stream, F enqueue) {
+  atsfft_plan_s::GraphEntry *hit = nullptr;
+  for (auto &g : plan->graphs)
+    if (g.kind == kind && g.batch == batch && std::memcmp(g.ptrs, key, sizeof(g.ptrs)) == 0) hit = &g;
+  if (!hit) {
+    if (plan->graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(plan->graphs.front().exec);
+      (void)hipGraphDestroy(plan->graphs.front().graph);
+      plan->graphs.erase(plan->graphs.begin());
+    }
+    if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(ATSFFT_ELAUNCH, "hipStreamCreateWithFlags failed");
+    atsfft_plan_s::GraphEntry e;
+    e.kind = kind;
+    e.batch = batch;
+    std::memcpy(e.ptrs, key, sizeof(e.ptrs));
+    e.graph = nullptr;
+    e.exec = nullptr;
+    if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ATSFFT_ELAUNCH, "hipStreamBeginCapture failed");
+    const hipError_t le = enqueue(plan->cap_stream);
+    const hipError_t ce = hipStreamEndCapture(plan->cap_stream, &e.graph);
+    if (le != hipSuccess || ce != hipSuccess || hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+      if (e.graph) (void)hipGraphDestroy(e.graph);
+      (void)hipGetLastError();
+      return fail(ATSFFT_ELAUNCH, "graph capture of the execute failed");
+    }
+    plan->graphs.push_back(e);
+    hit = &plan->graphs.back();
+  }
+  if (hipGraphLaunch(hit->exec, stream) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(ATSFFT_ELAUNCH, std::string("graph launch failed: ") + hipGetErrorString(e));
+  }
+  return ATSFFT_SUCCESS;
 }
 
 }  // namespace
@@ -587,6 +635,35 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   return ATSFFT_SUCCESS;
 }
 
+// The parameters of every length an uneven plan covers, for the execute with
+// device-side lengths: each length's own knobs and window tables, with the
+// workspace layout, bucket stride and probe-area offsets of the longest
+// (every signal's slice is the longest one's, so that a signal's slice is
+// found from its index alone).  1D plans without the residual test only.
+static atsfft_status build_dev_templates(atsfft_plan_s *p) {
+  if (p->d.ndim != 1 || p->d.res_tol > 0.0) return ATSFFT_SUCCESS;
+  const KParams top = make_params(p, make_layout(p, 1), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  std::vector<KParams> t;
+  uint32_t lo = p->logn;
+  while (lo > 0 && p->sub[lo - 1]) --lo;
+  for (uint32_t lg = lo; lg <= p->logn; ++lg) {
+    KParams q = make_params(p->sub[lg], top.lay, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    q.Bc_max = top.Bc_max;
+    std::memcpy(q.probe_off, top.probe_off, sizeof(q.probe_off));
+    if (q.probe_levels > top.probe_levels) return fail(ATSFFT_EINVAL, "a shorter length probes more levels");
+    t.push_back(q);
+  }
+  if (hipMalloc(&p->dev_tmpl, t.size() * sizeof(KParams)) != hipSuccess) {
+    p->dev_tmpl = nullptr;
+    return fail(ATSFFT_ENOMEM, "parameter table allocation failed");
+  }
+  if (hipMemcpy(p->dev_tmpl, t.data(), t.size() * sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ATSFFT_ELAUNCH, "parameter table upload failed");
+  p->dev_lg_lo = lo;
+  p->dev_lg_hi = p->logn;
+  return ATSFFT_SUCCESS;
+}
+
 atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   atsfft_status st = create_plan(out, d);
   if (st != ATSFFT_SUCCESS) return st;
@@ -618,6 +695,12 @@ atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d) {
       }
       p->sub[q->logn] = q;
     }
+    st = build_dev_templates(p);
+    if (st != ATSFFT_SUCCESS) {
+      free_plan(p);
+      *out = nullptr;
+      return st;
+    }
   }
   return ATSFFT_SUCCESS;
 }
@@ -642,41 +725,10 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
   KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev);
   const atsfft_desc &d = plan->d;
   if (d.flags & ATSFFT_FLAG_GRAPH) {
-    const void *key[7] = {x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev};
-    atsfft_plan_s::GraphEntry *hit = nullptr;
-    for (auto &g : plan->graphs)
-      if (g.batch == batch && std::memcmp(g.ptrs, key, sizeof(key)) == 0) hit = &g;
-    if (!hit) {
-      if (plan->graphs.size() >= kMaxGraphs) {
-        (void)hipGraphExecDestroy(plan->graphs.front().exec);
-        (void)hipGraphDestroy(plan->graphs.front().graph);
-        plan->graphs.erase(plan->graphs.begin());
-      }
-      if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(ATSFFT_ELAUNCH, "hipStreamCreateWithFlags failed");
-      atsfft_plan_s::GraphEntry e;
-      e.batch = batch;
-      std::memcpy(e.ptrs, key, sizeof(key));
-      e.graph = nullptr;
-      e.exec = nullptr;
-      if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(ATSFFT_ELAUNCH, "hipStreamBeginCapture failed");
-      const hipError_t le = launch_execute(P, d.dtype, batch, plan->cap_stream, nullptr, nullptr);
-      const hipError_t ce = hipStreamEndCapture(plan->cap_stream, &e.graph);
-      if (le != hipSuccess || ce != hipSuccess ||
-          hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
-        if (e.graph) (void)hipGraphDestroy(e.graph);
-        (void)hipGetLastError();
-        return fail(ATSFFT_ELAUNCH, "graph capture of the execute failed");
-      }
-      plan->graphs.push_back(e);
-      hit = &plan->graphs.back();
-    }
-    if (hipGraphLaunch(hit->exec, stream) != hipSuccess) {
-      hipError_t e = hipGetLastError();
-      return fail(ATSFFT_ELAUNCH, std::string("graph launch failed: ") + hipGetErrorString(e));
-    }
-    return ATSFFT_SUCCESS;
+    const void *key[9] = {x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev, nullptr, nullptr};
+    return graph_launch(plan, 0, batch, key, stream, [&](hipStream_t cs) {
+      return launch_execute(P, d.dtype, batch, cs, nullptr, nullptr);
+    });
   }
   std::array<hipEvent_t, 6> *rec = nullptr;
   if (d.flags & ATSFFT_FLAG_PROFILE) {
@@ -858,6 +910,54 @@ atsfft_status atsfft_execute_uneven(atsfft_plan_t plan, int32_t batch, const voi
       hipError_t e = hipGetLastError();
       return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
     }
+  }
+  return ATSFFT_SUCCESS;
+}
+
+// Workspace of atsfft_execute_uneven_dev: the per-length parameter table,
+// then one slice of the plan's longest length per signal.
+static size_t dev_table_bytes() { return align_up((size_t)32 * sizeof(KParams), 256); }
+
+atsfft_status atsfft_workspace_size_uneven_dev(atsfft_plan_t plan, int32_t batch, size_t *bytes) {
+  if (!plan || !bytes) return fail(ATSFFT_EINVAL, "null argument");
+  if (!plan->dev_tmpl) return fail(ATSFFT_EINVAL, "plan has no device-length uneven form (1D, n_min > 0, res_tol = 0)");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  *bytes = dev_table_bytes() + make_layout(plan, batch).total;
+  return ATSFFT_SUCCESS;
+}
+
+atsfft_status atsfft_execute_uneven_dev(atsfft_plan_t plan, int32_t batch, const void *x_dev,
+                                        const int64_t *offsets_dev, const int64_t *ns_dev, int64_t *locs_dev,
+                                        void *vals_dev, int32_t *count_dev, int32_t *khat_dev,
+                                        uint32_t *sig_status_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream) {
+  if (!plan) return fail(ATSFFT_EINVAL, "null plan");
+  if (!plan->dev_tmpl) return fail(ATSFFT_EINVAL, "plan has no device-length uneven form (1D, n_min > 0, res_tol = 0)");
+  if (plan->d.flags & ATSFFT_FLAG_PROFILE) return fail(ATSFFT_EINVAL, "no stage profile for the device-length uneven form");
+  if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
+  if (!x_dev || !offsets_dev || !ns_dev || !locs_dev || !vals_dev || !count_dev || !khat_dev || !sig_status_dev ||
+      !ws_dev)
+    return fail(ATSFFT_EINVAL, "null device pointer");
+  const size_t tb = dev_table_bytes();
+  const Layout lay = make_layout(plan, batch);
+  if (ws_bytes < tb + lay.total) return fail(ATSFFT_EINVAL, "workspace too small");
+  uint8_t *ws = static_cast<uint8_t *>(ws_dev);
+  KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws + tb);
+  P.x_off = offsets_dev;
+  P.ns = ns_dev;
+  P.devP = reinterpret_cast<const KParams *>(ws);
+  P.dev_lg_lo = plan->dev_lg_lo;
+  P.dev_lg_hi = plan->dev_lg_hi;
+  const KParams *tmpl = plan->dev_tmpl;
+  const int dtype = plan->d.dtype;
+  if (plan->d.flags & ATSFFT_FLAG_GRAPH) {
+    const void *key[9] = {x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev, offsets_dev, ns_dev};
+    return graph_launch(plan, 1, batch, key, stream, [&](hipStream_t cs) {
+      return launch_execute_dev(P, tmpl, dtype, batch, cs);
+    });
+  }
+  if (launch_execute_dev(P, tmpl, dtype, batch, stream) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(ATSFFT_ELAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   }
   return ATSFFT_SUCCESS;
 }

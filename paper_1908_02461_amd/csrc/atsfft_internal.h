@@ -34,6 +34,7 @@ enum : uint32_t {
   kSigEmpty = 8,
   kSigRetried = 16,
   kSigProbeTimeout = 32,
+  kSigBadLength = 64,
 };
 
 enum : int { kPhaseProbe = 0, kPhaseLoc = 1, kPhaseEst = 2 };
@@ -116,7 +117,15 @@ struct KParams {
   int32_t *count;
   int32_t *khat;
   uint32_t *status;
+  // uneven batches with device-side lengths: ns[sig] is signal sig's length
+  // and devP[log2 ns[sig]] the parameters of that length (written into the
+  // workspace by k_dev_setup), for log2 lengths dev_lg_lo..dev_lg_hi; null
+  // otherwise
+  const struct KParams *devP;
+  const int64_t *ns;
+  uint32_t dev_lg_lo, dev_lg_hi;
 };
+static_assert(sizeof(KParams) % 8 == 0, "KParams is copied in 8-byte words");
 
 // Host-side launchers (atsfft_kernels.hip).
 // mark(ctx, i) is called after stage i's launches are enqueued (i = 0 before
@@ -124,6 +133,10 @@ struct KParams {
 // 5 estimate); it may record an event on the stream.  May be null.
 typedef void (*StageMark)(void *ctx, int stage);
 hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s, StageMark mark, void *ctx);
+// One launch sequence over an uneven 1D batch whose lengths are on the device
+// (P.ns, P.devP set; tmpl: the plan's per-length parameters, device memory,
+// one per log2 length from P.dev_lg_lo).
+hipError_t launch_execute_dev(const KParams &P, const KParams *tmpl, int dtype, int batch, hipStream_t s);
 hipError_t launch_window_hat(const double *taps, int64_t w, int64_t n, int64_t c, double *out,
                              hipStream_t s);
 hipError_t prepare_kernels(int dtype, int ndim, size_t bucket_smem, size_t est_smem, size_t bwd_smem);

@@ -152,6 +152,22 @@ template <typename R> __device__ __forceinline__ const R *ghat_of(const KParams 
 }
 
 __device__ __forceinline__ uint32_t ilog2(uint32_t v) { return 31u - __clz(v); }
+
+// The parameters signal `sig` runs with: the launch's own, or (DEV, an uneven
+// batch whose lengths are on the device) those of the signal's length, which
+// k_dev_setup wrote into the workspace.  A length outside the plan's range
+// reads the nearest covered one; k_init marks such a signal and every kernel
+// skips it.
+template <bool DEV> __device__ __forceinline__ const KParams &params_of(const KParams &P, uint32_t sig) {
+  if constexpr (DEV) {
+    const int64_t n = P.ns[sig];
+    uint32_t lg = n > 0 ? 63u - (uint32_t)__clzll((unsigned long long)n) : 0u;
+    lg = min(max(lg, P.dev_lg_lo), P.dev_lg_hi);
+    return P.devP[lg];
+  } else {
+    return P;
+  }
+}
 __device__ __forceinline__ uint32_t bitrev(uint32_t v, uint32_t bits) {
   return bits ? (__brev(v) >> (32u - bits)) : 0u;
 }
@@ -279,9 +295,11 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
 
 // ------------------------------------------------------------- k_init ----
 
-__global__ void k_init(KParams P, int batch) {
+template <bool DEV>
+__global__ void k_init(KParams P0, int batch) {
   const int sig = blockIdx.x * blockDim.x + threadIdx.x;
   if (sig >= batch) return;
+  const KParams &P = params_of<DEV>(P0, (uint32_t)sig);
   SigState s;
   s.B = (int32_t)P.B0;
   s.k_prev = 0;
@@ -301,6 +319,15 @@ __global__ void k_init(KParams P, int batch) {
     s.B_star = (int32_t)P.fixed_B;
     s.khat = (int32_t)P.fixed_k;
     if (s.khat <= 0) s.status |= kSigEmpty;
+  }
+  if constexpr (DEV) {
+    // a length that is not a power of two the plan covers: nothing runs
+    const int64_t n = P0.ns[sig];
+    if (n != (int64_t)P.n) {
+      s.done = 1;
+      s.khat = 0;
+      s.status |= kSigBadLength | kSigEmpty;
+    }
   }
   *state_of(P, sig) = s;
   // a probe level's count is -1 until its k_bucket workgroup stores it
@@ -357,9 +384,11 @@ __device__ __forceinline__ void neumaier_add(float &s, float &c, float v) {
 
 // COMP (FP32 only): every accumulation carries a Neumaier compensation term
 // through the wraps and the LDS reduction, and the partial is s + c.
-template <typename R, int NDIM, int LG, bool COMP = false, bool MAIN = true>
-__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
+template <typename R, int NDIM, int LG, bool COMP = false, bool MAIN = true, bool DEV = false>
+__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter) {
   using C = typename CT<R>::C;
+  const uint32_t sig = blockIdx.z;
+  const KParams &P = params_of<DEV>(P0, sig);
   constexpr bool main_phase = MAIN;
   static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
   // 2D probe levels read few rows more than once: one slab, no row filter
@@ -367,7 +396,6 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P, int iter) {
   const uint32_t slab = blockIdx.x % NS;
   const uint32_t slot = blockIdx.x / NS;
   const uint32_t nslots = gridDim.x / NS;
-  const uint32_t sig = blockIdx.z;
   const SigState st = *state_of(P, sig);  // one 64-byte read
   uint32_t B, alpha, nl = 1;
   Draw d0[LG], d1[LG];
@@ -1077,11 +1105,12 @@ __device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
 // then for probe and location loops m_b = |y_hat_b|^2, the noise-floor
 // threshold T, and either the local-maximum count with the adaptive-B
 // control (probe) or the top-num cutoff J (location loops).
-template <typename R, int NDIM>
-__global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_phase, int iter) {
+template <typename R, int NDIM, bool DEV = false>
+__global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_phase, int iter) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t sig = blockIdx.y;
+  const KParams &P = params_of<DEV>(P0, sig);
   const uint32_t loop = blockIdx.x;
   const uint32_t level = (uint32_t)iter + blockIdx.x;
   SigState *st = state_of(P, sig);
@@ -1301,12 +1330,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P, int main_p
         __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // the last of the round's workgroups of this signal applies the rule;
       // it reads only the counts, themselves atomics, so no fence (an
-      // agent-scope fence writes back and invalidates the L2)
+      // agent-scope fence writes back and invalidates the L2).  A signal has
+      // as many workgroups in the round as it has levels in it (a shorter
+      // signal of an uneven batch may have fewer levels than the launch).
+      const uint32_t in_round = min((uint32_t)iter + gridDim.x, P.probe_levels) - (uint32_t)iter;
       const uint32_t prior = __hip_atomic_fetch_add(&st->round_blocks, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-      if (prior + 1u == gridDim.x) {
+      if (prior + 1u == in_round) {
         __hip_atomic_store(&st->round_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        probe_control<NDIM>(P, sig, iter, iter + (int)gridDim.x);
+        probe_control<NDIM>(P, sig, iter, iter + (int)in_round);
       }
     }
     return;
@@ -1448,8 +1480,9 @@ constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x colu
 // and per column instead of two per pair.  SMALL: every hash product fits
 // 24-bit operands (1D n <= 2^24, and 2D), so the full-rate 24-bit multiply
 // gives the product modulo n.
-template <int NDIM, bool SMALL>
-__global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P) {
+template <int NDIM, bool SMALL, bool DEV = false>
+__global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
+  const KParams &P = params_of<DEV>(P0, blockIdx.z);
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
   constexpr int K = kVoteIlp;
   constexpr uint32_t KB = kVoteBlock2d;
@@ -1709,11 +1742,12 @@ __device__ __forceinline__ EstTerm<R> est_term(const uint32_t *es, uint32_t f, u
 // the real parts is the value whose rank among the lanes' (ties by loop
 // order, unused lanes +inf) is L_est / 2, and likewise for the imaginary
 // parts.
-template <typename R, int NDIM, int ML>
-__global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P) {
+template <typename R, int NDIM, int ML, bool DEV = false>
+__global__ __launch_bounds__(kEstThreads) void k_estimate(KParams P0) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t sig = blockIdx.y, grp = blockIdx.x;
+  const KParams &P = params_of<DEV>(P0, sig);
   SigState *st = state_of(P, sig);
   const SigState s = *st;
   __syncthreads();
@@ -2371,13 +2405,13 @@ static uint32_t ilog2_host_u32(uint32_t v) {
   return r;
 }
 
-template <typename R, int NDIM>
+template <typename R, int NDIM, bool DEV = false>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
   const size_t esmem = estimate_smem_bytes(P.max_out);
   const uint32_t hash_blocks = kSlabs * max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
-  hipLaunchKernelGGL(k_init, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
+  hipLaunchKernelGGL(k_init<DEV>, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
   if (!P.fixed) {
     // rounds of probe levels: every level up to B = probe_first at once, then
     // probe_step levels per round
@@ -2392,12 +2426,12 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       constexpr uint32_t kProbeSlabs = NDIM == 1 ? (uint32_t)kSlabs : 1u;
       const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
       if (sizeof(R) == 4 && P.comp)
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false>), dim3(kProbeSlabs * slots, hi - lo, batch),
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false, DEV>), dim3(kProbeSlabs * slots, hi - lo, batch),
                            dim3(kHashThreads), 0, s, P, (int)lo);
       else
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false>), dim3(kProbeSlabs * slots, hi - lo, batch),
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(kProbeSlabs * slots, hi - lo, batch),
                            dim3(kHashThreads), 0, s, P, (int)lo);
-      hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       lo = hi;
     }
   }
@@ -2418,7 +2452,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const size_t vsmem = vote_smem_bytes(P.L_loc, P.Bc_max);
   // 2D rows staged in LDS when the row fits and the input is 16-byte aligned
   const size_t rows_smem = std::max<size_t>((size_t)P.n * sizeof(typename CT<R>::C), 2 * kHashThreads * sizeof(R));
-  const bool rows = NDIM == 2 && P.rows2d_ok && !P.x_off && (reinterpret_cast<uintptr_t>(P.x) & 15u) == 0 && !P.comp;
+  const bool rows = !DEV && NDIM == 2 && P.rows2d_ok && !P.x_off && (reinterpret_cast<uintptr_t>(P.x) & 15u) == 0 && !P.comp;
   const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
   auto main_pass = [&](const KParams &Q0, bool marks) {
     KParams Q = Q0;
@@ -2437,32 +2471,32 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hipLaunchKernelGGL((k_hash2d_rows<R>), dim3(1u << (ilog2_host_u32(P.Bc_max) / 2), loops, batch),
                          dim3(kHashThreads), rows_smem, s, Q);
     else if (sizeof(R) == 4 && Q.comp)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4>), hgrid1, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, true, DEV>), hgrid1, dim3(kHashThreads), 0, s, Q, 0);
     else if (NDIM == 2 || LG == 1)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     else if (LG == 2)
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     else
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
     if (marks && mark) mark(ctx, 2);
-    hipLaunchKernelGGL((k_bucket<R, NDIM>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
+    hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
     if (marks && mark) mark(ctx, 3);
     if (NDIM == 2 || P.logn <= 24)
-      hipLaunchKernelGGL((k_vote<NDIM, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+      hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
     else
-      hipLaunchKernelGGL((k_vote<NDIM, false>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+      hipLaunchKernelGGL((k_vote<NDIM, false, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
     if (marks && mark) mark(ctx, 4);
     // estimate workgroups per signal: more for small batches, up to 32
     const uint32_t est_groups = std::min<uint32_t>(32u, std::max<uint32_t>((uint32_t)kEstGroups, 128u / (uint32_t)batch));
     if (Q.L_est <= 8)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 8>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 8, DEV>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
     else if (Q.L_est <= 16)
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 16>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 16, DEV>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
     else
-      hipLaunchKernelGGL((k_estimate<R, NDIM, 32>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
+      hipLaunchKernelGGL((k_estimate<R, NDIM, 32, DEV>), dim3(est_groups, batch), dim3(kEstThreads), esmem, s, Q);
   };
   main_pass(P, true);
-  if (P.res_tol > 0.0) {
+  if (!DEV && P.res_tol > 0.0) {
     // residual test after every pass; a pass r > 0 runs only the signals the
     // test sent back at 2 B_star
     const size_t rsmem = residual_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
@@ -2482,6 +2516,38 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
 hipError_t launch_execute(const KParams &P, int dtype, int batch, hipStream_t s, StageMark mark, void *ctx) {
   if (dtype == 0) return P.ndim == 1 ? run<float, 1>(P, batch, s, mark, ctx) : run<float, 2>(P, batch, s, mark, ctx);
   return P.ndim == 1 ? run<double, 1>(P, batch, s, mark, ctx) : run<double, 2>(P, batch, s, mark, ctx);
+}
+
+// The per-length parameters of a device-driven uneven call: block i copies
+// the plan's template for log2 length dev_lg_lo + i into the workspace table
+// and completes it with the call's buffers.
+__global__ void k_dev_setup(KParams P, const KParams *tmpl) {
+  const uint32_t lg = P.dev_lg_lo + blockIdx.x;
+  KParams *q = const_cast<KParams *>(P.devP) + lg;
+  const uint64_t *src = reinterpret_cast<const uint64_t *>(tmpl + blockIdx.x);
+  uint64_t *dst = reinterpret_cast<uint64_t *>(q);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(KParams) / 8); i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    q->ws = P.ws;
+    q->x = P.x;
+    q->x_off = P.x_off;
+    q->sig_map = nullptr;
+    q->locs = P.locs;
+    q->vals = P.vals;
+    q->count = P.count;
+    q->khat = P.khat;
+    q->status = P.status;
+    q->pass = 0;
+    q->devP = nullptr;
+    q->ns = P.ns;
+  }
+}
+
+hipError_t launch_execute_dev(const KParams &P, const KParams *tmpl, int dtype, int batch, hipStream_t s) {
+  if (P.ndim != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dev_setup, dim3(P.dev_lg_hi - P.dev_lg_lo + 1), dim3(256), 0, s, P, tmpl);
+  return dtype == 0 ? run<float, 1, true>(P, batch, s, nullptr, nullptr) : run<double, 1, true>(P, batch, s, nullptr, nullptr);
 }
 
 }  // namespace atsfft
