@@ -35,6 +35,7 @@ struct atsfft_plan_s {
   uint32_t gather_blocks;  // adjoint gather: most workgroups per signal
   uint32_t probe_first; // first probe round covers B up to this
   uint32_t probe_step;  // probe levels per later round
+  uint32_t probe_slabs; // 1D probe levels: address slabs
   uint32_t probe_spin;  // sleeps before the probe control gives up waiting for a count
   int32_t probe_drop;   // test hook: probe level whose count is never recorded (-1: none)
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
@@ -301,6 +302,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.gather_blocks = plan->gather_blocks;
   P.probe_first = plan->probe_first;
   P.probe_step = plan->probe_step;
+  P.probe_slabs = plan->probe_slabs;
   P.probe_spin = plan->probe_spin;
   P.probe_drop = plan->probe_drop;
   P.tile_slots = plan->tile_slots;
@@ -523,6 +525,11 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   if (const char *env = std::getenv("ATSFFT_PROBE_STEP")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 32) p->probe_step = (uint32_t)v;
+  }
+  p->probe_slabs = kSlabs;
+  if (const char *env = std::getenv("ATSFFT_PROBE_SLABS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v == 1 || v == kSlabs) p->probe_slabs = (uint32_t)v;
   }
   p->probe_spin = 1u << 20;
   if (const char *env = std::getenv("ATSFFT_PROBE_SPIN")) {

@@ -91,6 +91,7 @@ struct KParams {
   uint32_t gather_blocks;  // adjoint gather: most workgroups per signal (the rest by grid stride)
   uint32_t probe_first;  // first probe round: every level with B (per axis) up to this
   uint32_t probe_step;   // probe levels per later round
+  uint32_t probe_slabs;  // 1D probe levels: address slabs (1 or kSlabs), each a partial per bucket
   uint32_t probe_levels;               // bucket counts B0 * 2^i, i < probe_levels
   uint32_t probe_spin;   // sleeps before the probe control stops waiting for a level's count
   int32_t probe_drop;    // test hook: probe level whose count is never recorded (-1: none)

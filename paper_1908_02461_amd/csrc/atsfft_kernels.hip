@@ -385,25 +385,40 @@ __device__ __forceinline__ void neumaier_add(float &s, float &c, float v) {
 // COMP (FP32 only): every accumulation carries a Neumaier compensation term
 // through the wraps and the LDS reduction, and the partial is s + c.
 template <typename R, int NDIM, int LG, bool COMP = false, bool MAIN = true, bool DEV = false>
-__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter) {
+__global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter, int iter_hi) {
   using C = typename CT<R>::C;
   const uint32_t sig = blockIdx.z;
   const KParams &P = params_of<DEV>(P0, sig);
   constexpr bool main_phase = MAIN;
   static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
-  // 2D probe levels read few rows more than once: one slab, no row filter
-  constexpr uint32_t NS = (MAIN || NDIM == 1) ? (uint32_t)kSlabs : 1u;
+  // 2D probe levels read few rows more than once: one slab, no row filter;
+  // 1D probe levels as the plan says (their lines are cold and rarely
+  // touched twice, so one slab spares the other workgroups' address scans)
+  const uint32_t NS = MAIN ? (uint32_t)kSlabs : NDIM == 1 ? P.probe_slabs : 1u;
   const uint32_t slab = blockIdx.x % NS;
-  const uint32_t slot = blockIdx.x / NS;
-  const uint32_t nslots = gridDim.x / NS;
+  uint32_t slot = blockIdx.x / NS;
+  uint32_t nslots = gridDim.x / NS;
+  // a probe round's grid lists (level, slot) pairs, each level with as many
+  // slots as it has 64-bucket tiles (at most tile_slots), counted with the
+  // launch's B0 (a shorter signal of an uneven batch has no more tiles)
+  uint32_t level = (uint32_t)iter;
+  if (!main_phase) {
+    for (;;) {
+      const uint32_t Bl = P0.B0 << level;
+      const uint32_t tl = ((NDIM == 1 ? Bl : Bl * Bl) + kTile - 1) / kTile;
+      nslots = max(1u, min(P0.tile_slots, tl));
+      if (slot < nslots || level + 1u >= (uint32_t)iter_hi) break;
+      slot -= nslots;
+      ++level;
+    }
+  }
   const SigState st = *state_of(P, sig);  // one 64-byte read
   uint32_t B, alpha, nl = 1;
   Draw d0[LG], d1[LG];
   C *y[LG];
   size_t sstride;
   if (!main_phase) {
-    const uint32_t level = (uint32_t)iter + blockIdx.y;
-    if (st.done || level >= P.probe_levels) return;
+    if (slot >= nslots || st.done || level >= P.probe_levels) return;
     B = P.B0 << level;
     alpha = P.alpha_probe;
     d0[0] = draw(P, sig, kPhaseProbe, (int)level, 0);
@@ -470,7 +485,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter) {
 #pragma unroll
             for (int u = 0; u < kHashU; ++u) {
               const uint32_t aq = a[q];
-              const bool pp = (uint32_t)q < nl && r0 + 4u * u < wraps && (aq >> slab_shift) == slab;
+              const bool pp = (uint32_t)q < nl && r0 + 4u * u < wraps && (NS == 1u || (aq >> slab_shift) == slab);
               a[q] = (aq + step[q]) & mask;
               v[q][u].x = 0;
               v[q][u].y = 0;
@@ -1140,7 +1155,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   // hash leaves one per row wrap, the row hash one in all, k_hash kSlabs; the
   // compensated FP32 fold adds them in FP64.  kSumU buckets per thread have
   // their loads issued together.
-  const uint32_t nsl = !main_phase ? (NDIM == 1 ? (uint32_t)kSlabs : 1u)
+  const uint32_t nsl = !main_phase ? (NDIM == 1 ? P.probe_slabs : 1u)
                        : P.rows2d == 1 ? 1u
                        : P.rows2d == 2 ? (min(P.alpha * B, P.n) >> logB)
                                        : (uint32_t)kSlabs;
@@ -2421,16 +2436,20 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       if (lo == 0)
         while (hi < P.probe_levels && (P.B0 << hi) <= P.probe_first) ++hi;
       hi = min(hi, P.probe_levels);
-      const uint32_t Bt = P.B0 << (hi - 1);
-      const uint32_t Bct = NDIM == 1 ? Bt : Bt * Bt;
-      constexpr uint32_t kProbeSlabs = NDIM == 1 ? (uint32_t)kSlabs : 1u;
-      const uint32_t slots = max(1u, min(P.tile_slots, (Bct + kTile - 1) / kTile));
+      // (level, slot) pairs: each level as many slots as it has tiles, at
+      // most tile_slots (so that small levels launch no idle workgroups)
+      uint32_t slots = 0;
+      for (uint32_t l = lo; l < hi; ++l) {
+        const uint32_t Bl = P.B0 << l;
+        slots += max(1u, min(P.tile_slots, ((NDIM == 1 ? Bl : Bl * Bl) + kTile - 1) / kTile));
+      }
+      const uint32_t kProbeSlabs = NDIM == 1 ? P.probe_slabs : 1u;
       if (sizeof(R) == 4 && P.comp)
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false, DEV>), dim3(kProbeSlabs * slots, hi - lo, batch),
-                           dim3(kHashThreads), 0, s, P, (int)lo);
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false, DEV>), dim3(kProbeSlabs * slots, 1, batch),
+                           dim3(kHashThreads), 0, s, P, (int)lo, (int)hi);
       else
-        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(kProbeSlabs * slots, hi - lo, batch),
-                           dim3(kHashThreads), 0, s, P, (int)lo);
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(kProbeSlabs * slots, 1, batch),
+                           dim3(kHashThreads), 0, s, P, (int)lo, (int)hi);
       hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       lo = hi;
     }
@@ -2471,13 +2490,13 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hipLaunchKernelGGL((k_hash2d_rows<R>), dim3(1u << (ilog2_host_u32(P.Bc_max) / 2), loops, batch),
                          dim3(kHashThreads), rows_smem, s, Q);
     else if (sizeof(R) == 4 && Q.comp)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, true, DEV>), hgrid1, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, true, DEV>), hgrid1, dim3(kHashThreads), 0, s, Q, 0, 0);
     else if (NDIM == 2 || LG == 1)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
     else if (LG == 2)
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
     else
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0);
+      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
     if (marks && mark) mark(ctx, 2);
     hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
     if (marks && mark) mark(ctx, 3);
