@@ -22,6 +22,7 @@ struct atsfft_plan_s {
   int device;
   uint32_t logn;
   uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
+  uint32_t big;      // 2D fixed-B arrays above the LDS-resident size: DFTs and cutoffs in device memory
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t tab_host[128];  // element offsets by log2 B (passed in the kernel arguments)
@@ -73,6 +74,7 @@ namespace {
 
 thread_local std::string g_err = "";
 constexpr size_t kMaxGraphs = 64;  // call shapes kept per plan under ATSFFT_FLAG_GRAPH
+constexpr uint32_t kBigStandIn = 4096;  // bucket count whose LDS sizes a large-array plan's unused kernels
 
 atsfft_status fail(atsfft_status s, const std::string &msg) {
   g_err = msg;
@@ -166,8 +168,8 @@ atsfft_status validate(const atsfft_desc *d) {
     return fail(ATSFFT_EINVAL, "the residual test needs B_max a power of two in [2, n/2] (2D: [4, N/2])");
   const int64_t Bbig = main_bmax(d);
   const int64_t Bc = d->ndim == 1 ? Bbig : Bbig * Bbig;
-  if (Bc > (int64_t)kBucketThreads * kBucketMaxPer)
-    return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384");
+  if (Bc > (int64_t)kBucketThreads * kBucketMaxPer && !(d->ndim == 2 && fixed && Bbig <= (int64_t)kBigMax))
+    return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384 (2D with FIXED_B: B <= 1024)");
   if (d->alpha < 2 || d->alpha > 1024 || (d->alpha & 1)) return fail(ATSFFT_EINVAL, "alpha must be even in [2, 1024]");
   if (d->L_loc < 1 || d->L_loc > kMaxLoops - 1) return fail(ATSFFT_EINVAL, "L_loc must be in [1, 31]");
   if (d->L_est < 1 || d->L_est > kMaxLoops - 1 || (d->L_est % 2) == 0)
@@ -315,6 +317,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.res_reach = residual_reach(&d);
   P.pass = 0;
   P.comp = (d.flags & ATSFFT_FLAG_COMPENSATED) && d.dtype == ATSFFT_C64 ? 1u : 0u;
+  P.big = plan->big;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;
@@ -542,14 +545,33 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     if (v >= 0 && v < kMaxProbe) p->probe_drop = (int32_t)v;
   }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
-  p->bwd_smem = bwd_smem_bytes(d->dtype, p->Bc_max, (uint32_t)d->max_out);
+  p->big = 0;
   if (p->bucket_smem > prop.sharedMemPerBlock) {
-    char msg[160];
-    std::snprintf(msg, sizeof(msg), "B_max^ndim = %u needs %zu bytes of LDS, device has %zu", p->Bc_max,
-                  p->bucket_smem, (size_t)prop.sharedMemPerBlock);
-    free_plan(p);
-    return fail(ATSFFT_EINVAL, msg);
+    // 2D with a fixed B (the known-k form at the sparse FFT's bucket count):
+    // the bucket arrays live in device memory; needs rows streamed once
+    // (a row fits the row buffer, w / B <= kSlabs partials) and no probe,
+    // residual test, compensated fold, uneven lengths or adjoint
+    const uint64_t row_bytes = (uint64_t)n * (d->dtype == ATSFFT_C64 ? 8 : 16);
+    const bool big_ok = d->ndim == 2 && fixed && d->res_tol == 0.0 && d->n_min == 0 &&
+                        !(d->flags & ATSFFT_FLAG_COMPENSATED) && Bbig <= (int64_t)kBigMax &&
+                        d->alpha <= kSlabs && row_bytes <= kRowBytes &&
+                        big_cols_smem(d->dtype, (uint32_t)Bbig) <= prop.sharedMemPerBlock &&
+                        big_stats_smem((uint32_t)Bbig) <= prop.sharedMemPerBlock;
+    if (!big_ok) {
+      char msg[200];
+      std::snprintf(msg, sizeof(msg),
+                    "B_max^ndim = %u needs %zu bytes of LDS, device has %zu (larger arrays: 2D, FIXED_B, "
+                    "B <= %u, alpha <= 8, no residual test, compensation or uneven lengths)",
+                    p->Bc_max, p->bucket_smem, (size_t)prop.sharedMemPerBlock, kBigMax);
+      free_plan(p);
+      return fail(ATSFFT_EINVAL, msg);
+    }
+    p->big = 1;
+    // k_bucket and the adjoint do not run on such a plan; their LDS settings
+    // are those of a small array (kBigStandIn buckets), within the device's
+    p->bucket_smem = bucket_smem_bytes(d->dtype, kBigStandIn);
   }
+  p->bwd_smem = bwd_smem_bytes(d->dtype, p->big ? kBigStandIn : p->Bc_max, (uint32_t)d->max_out);
 
   // window tables for every bucket count a loop may use
   std::vector<double> taps_all, ghat_all;
@@ -729,6 +751,8 @@ atsfft_status atsfft_execute_batched(atsfft_plan_t plan, int32_t batch, const vo
     return fail(ATSFFT_EINVAL, "null device pointer");
   const Layout lay = make_layout(plan, batch);
   if (ws_bytes < lay.total) return fail(ATSFFT_EINVAL, "workspace too small");
+  if (plan->big && (reinterpret_cast<uintptr_t>(x_dev) & 15u))
+    return fail(ATSFFT_EINVAL, "x must be 16-byte aligned for bucket arrays above the LDS-resident size");
   KParams P = make_params(plan, lay, x_dev, locs_dev, vals_dev, count_dev, khat_dev, sig_status_dev, ws_dev);
   const atsfft_desc &d = plan->d;
   if (d.flags & ATSFFT_FLAG_GRAPH) {
@@ -784,6 +808,8 @@ atsfft_status atsfft_execute_batched_noalloc(atsfft_plan_t plan, int32_t batch, 
                   (int)batch, lay.total, kScratchBytes);
     return fail(ATSFFT_EINVAL, msg);
   }
+  if (plan->big && (reinterpret_cast<uintptr_t>(x_dev) & 15u))
+    return fail(ATSFFT_EINVAL, "x must be 16-byte aligned for bucket arrays above the LDS-resident size");
   if (!plan->scratch)
     return fail(ATSFFT_ELAUNCH, std::string("fixed workspace address lookup failed: ") +
                                     hipGetErrorString(plan->scratch_err));
@@ -807,6 +833,7 @@ atsfft_status atsfft_backward(atsfft_plan_t plan, int32_t batch, const void *gra
   if (!plan) return fail(ATSFFT_EINVAL, "null plan");
   if (batch < 1 || batch > plan->d.max_batch) return fail(ATSFFT_EINVAL, "batch outside [1, max_batch]");
   if (!grad_vals_dev || !ws_dev || !grad_x_dev) return fail(ATSFFT_EINVAL, "null device pointer");
+  if (plan->big) return fail(ATSFFT_ENOTSUPPORTED, "no adjoint for bucket arrays above the LDS-resident size");
   const Layout lay = make_layout(plan, batch);
   KParams P = make_params(plan, lay, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, const_cast<void *>(ws_dev));
   if (launch_backward(P, plan->d.dtype, batch, grad_vals_dev, grad_x_dev, stream) != hipSuccess) {

@@ -23,6 +23,7 @@ constexpr size_t kGatherLdsBytes = 65536;  // adjoint gather: most LDS for a sta
 constexpr int kRowTaps = 8;                // 2D row hash: column wraps per thread, at most
 constexpr uint32_t kRowBytes = 64u << 10;  // 2D row hash: largest row staged in LDS
 constexpr int kMaxOut = 16384;
+constexpr uint32_t kBigMax = 1024;  // 2D bucket arrays in device memory: largest B per axis
 // fixed device workspace of atsfft_execute_batched_noalloc (bytes per device)
 constexpr size_t kScratchBytes = (size_t)64 << 20;
 constexpr int kMaxDevices = 64;
@@ -102,6 +103,7 @@ struct KParams {
   uint32_t res_reach;    // model reach in buckets to each side of a frequency's own
   uint32_t pass;         // the pass this launch runs (signals of other passes skip)
   uint32_t comp;         // FP32 fold sums compensated (Neumaier), slab partials added in FP64
+  uint32_t big;          // 2D bucket arrays above the LDS-resident size: DFTs and cutoffs in device memory
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
   int64_t tab[128];    // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),
@@ -148,6 +150,9 @@ size_t bucket_smem_bytes(int dtype, uint32_t Bc_max);
 size_t estimate_smem_bytes(uint32_t max_out);
 size_t residual_smem_bytes(int dtype, uint32_t Bc_max);
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);
+size_t big_rows_smem(int dtype, uint32_t B);
+size_t big_cols_smem(int dtype, uint32_t B);
+size_t big_stats_smem(uint32_t B);
 // Device address of `device`'s fixed workspace (kScratchBytes), looked up once
 // per device; `device` must be the current device on the first call for it.
 hipError_t scratch_address(int device, void **ptr);

@@ -207,8 +207,22 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
   return r;
 }
 
-// The k-th smallest (0-based) of the values of m[0..cnt) in LDS that exceed
-// `above` (default: all), by most-significant-digit radix selection on the
+// Exclusive prefix sum over the block in thread order; `sh` holds one word per
+// wave, from word 8 on (words 0..7 are left to the callers' other uses).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh) {
+  const uint32_t incl = wave_incl_scan(v);
+  const uint32_t wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 63) sh[8 + wave] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t w = 0; w < wave; ++w) before += sh[8 + w];
+  (void)nw;
+  __syncthreads();
+  return before + incl - v;
+}
+
+// The k-th smallest (0-based) of the values of m[0..cnt) (in LDS or device
+// memory) that exceed `above` (default: all), by most-significant-digit radix selection on the
 // bit patterns (the values are non-negative, so their patterns order like the
 // values).  When the keys' range [lo, hi] is known, the digits are taken of
 // key - lo from the top bit of hi - lo, so that the first pass spreads the
@@ -916,8 +930,8 @@ __global__ __launch_bounds__(kHashThreads) void k_hash2d_rows(KParams P) {
 // rows are read once: non-temporal loads, so that they do not push the
 // partials (read back by k_bucket) out of the caches
 typedef float nt4 __attribute__((ext_vector_type(4)));
-template <typename R, int U>
-__global__ __launch_bounds__(kHashThreads) void k_hash2d_stream(KParams P) {
+template <typename R, int U, int NT = kHashThreads>
+__global__ __launch_bounds__(NT) void k_hash2d_stream(KParams P) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_inv0[2 * kMaxLoops], s_tau0[2 * kMaxLoops], s_sig1[2 * kMaxLoops], s_tau1[2 * kMaxLoops];
@@ -1472,6 +1486,192 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   }
 }
 
+// ------------------------------------------------ large 2D bucket arrays ----
+
+// 2D bucket arrays above the LDS-resident size (B x B > kBucketThreads *
+// kBucketMaxPer, up to 1024 x 1024; the known-k form at the sparse FFT's
+// bucket count, B = sqrt(N k) per axis) are transformed and cut in device
+// memory: k_big_rows adds a bucket row's row-wrap partials and takes its
+// B-point DFT along b2, k_big_cols takes the B-point DFTs along b1 of a block
+// of kBigCols columns, and k_big_stats (location loops) computes m = |y|^2,
+// the noise floor, T and the top-num cutoff J with the selects run over
+// device memory.  The results sit where k_bucket leaves them (y_hat in the
+// first partial slot, m in the second as scratch, J as bitmap and list).
+
+// one workgroup per (bucket row b1, loop, signal)
+template <typename R>
+__global__ __launch_bounds__(256) void k_big_rows(KParams P) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *buf = reinterpret_cast<C *>(smem);
+  const uint32_t b1 = blockIdx.x, loop = blockIdx.y, sig = blockIdx.z;
+  const SigState st = *state_of(P, sig);
+  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
+  const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
+  if (b1 >= B) return;
+  const uint32_t wraps = min(P.alpha * B, P.n) >> logB;
+  C *y = ymain_of<C>(P, sig, loop);
+  const size_t row = (size_t)b1 << logB;
+  for (uint32_t b2 = threadIdx.x; b2 < B; b2 += blockDim.x) {
+    C v = y[row + b2];
+    for (uint32_t r = 1; r < wraps; ++r) {
+      const C u = y[(size_t)r * P.Bc_max + row + b2];
+      v.x += u.x;
+      v.y += u.y;
+    }
+    buf[lds_at<true>(bitrev(b2, logB))] = v;
+  }
+  __syncthreads();
+  fft_axis<R, true>(buf, logB, 1, 0, 1);
+  for (uint32_t b2 = threadIdx.x; b2 < B; b2 += blockDim.x) y[row + b2] = buf[lds_at<true>(b2)];
+}
+
+template <typename R> constexpr uint32_t big_cols() { return sizeof(R) == 4 ? 16u : 8u; }
+
+// one workgroup per (block of big_cols() columns, loop, signal)
+template <typename R>
+__global__ __launch_bounds__(256) void k_big_cols(KParams P) {
+  using C = typename CT<R>::C;
+  constexpr uint32_t CB = big_cols<R>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *buf = reinterpret_cast<C *>(smem);
+  const uint32_t loop = blockIdx.y, sig = blockIdx.z;
+  const SigState st = *state_of(P, sig);
+  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
+  const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
+  const uint32_t c0 = blockIdx.x * CB;
+  if (c0 >= B) return;
+  C *y = ymain_of<C>(P, sig, loop);
+  for (uint32_t i = threadIdx.x; i < B * CB; i += blockDim.x) {
+    const uint32_t b1 = i / CB, c = i % CB;
+    buf[lds_at<true>(bitrev(b1, logB) * CB + c)] = y[((size_t)b1 << logB) + c0 + c];
+  }
+  __syncthreads();
+  fft_axis<R, true>(buf, logB, CB, 1, CB);
+  for (uint32_t i = threadIdx.x; i < B * CB; i += blockDim.x) {
+    const uint32_t b1 = i / CB, c = i % CB;
+    y[((size_t)b1 << logB) + c0 + c] = buf[lds_at<true>(b1 * CB + c)];
+  }
+}
+
+// one 1024-thread workgroup per (location loop, signal): the same threshold
+// and cutoff as k_bucket's location role, over device memory
+template <typename R>
+__global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
+  using C = typename CT<R>::C;
+  using K = typename CT<R>::K;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem);  // 512 words
+  uint32_t *sh = hist + 512;                             // 32 words
+  K *wk = reinterpret_cast<K *>(sh + 32);                // 2 keys per wave
+  uint32_t *cg = reinterpret_cast<uint32_t *>(wk + 2 * (kBucketThreads / 64));  // per-chunk counts
+  const uint32_t loop = blockIdx.x, sig = blockIdx.y;
+  SigState *st = state_of(P, sig);
+  if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
+  const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
+  const uint32_t Bc = B * B, nch = Bc >> 6;
+  uint32_t *ce = cg + nch;
+  const uint32_t tid = threadIdx.x, T = blockDim.x, lane = tid & 63u, wave = tid >> 6, nw = T >> 6;
+  C *y = ymain_of<C>(P, sig, loop);
+  R *m = reinterpret_cast<R *>(y + P.Bc_max);  // the second partial slot, free after k_big_rows
+  K kmax = 0, kmin = ~(K)0;
+  for (uint32_t b = tid; b < Bc; b += T) {
+    const C v = y[b];
+    const R mb = v.x * v.x + v.y * v.y;
+    m[b] = mb;
+    kmax = max(kmax, key_of(mb));
+    kmin = min(kmin, key_of(mb));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    kmax = max(kmax, (K)__shfl_xor(kmax, o));
+    kmin = min(kmin, (K)__shfl_xor(kmin, o));
+  }
+  if (lane == 0) {
+    wk[2 * wave] = kmax;
+    wk[2 * wave + 1] = kmin;
+  }
+  __syncthreads();
+  for (uint32_t w = 0; w < nw; ++w) {
+    kmax = max(kmax, wk[2 * w]);
+    kmin = min(kmin, wk[2 * w + 1]);
+  }
+  // threshold: as k_bucket (noise floor from the floor(q (Bc-1))-th order
+  // statistic, c_noise = ln(Bc / noise_rate), relative floor rho * max m)
+  const R mmax = val_of(kmax);
+  const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
+  const R floor_m = block_kth_smallest<R>(m, Bc, qi, hist, sh, (R)-1, kmin, kmax);
+  const double c_noise = log((double)Bc / P.noise_rate);
+  const double t1 = c_noise * ((double)floor_m / P.neg_log1mq);
+  const double t2 = P.rho * (double)mmax;
+  const double Td = t1 > t2 ? t1 : t2;
+  const R Tr = (R)Td;
+  if (tid == 0) tloc_of(P, sig)[loop] = Td;
+  uint32_t above = 0;
+  for (uint32_t b = tid; b < Bc; b += T) above += m[b] > Tr ? 1u : 0u;
+  const uint32_t n_above = block_sum(above, &sh[4]);
+  uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
+  if (num > Bc) num = Bc;
+  R v = Tr;
+  uint32_t need = 0;
+  if (n_above > num) {
+    v = block_kth_smallest<R>(m, Bc, n_above - num, hist, sh, Tr);
+    uint32_t gt = 0;
+    for (uint32_t b = tid; b < Bc; b += T) gt += m[b] > v ? 1u : 0u;
+    need = num - block_sum(gt, &sh[4]);
+  }
+  // per 64-bucket chunk: buckets above v and buckets equal to v (a wave a chunk)
+  for (uint32_t c = wave; c < nch; c += nw) {
+    const R mb = m[(c << 6) + lane];
+    const unsigned long long g = __ballot(mb > v);
+    const unsigned long long e = __ballot(need > 0u && mb == v);
+    if (lane == 0) {
+      cg[c] = (uint32_t)__popcll(g);
+      ce[c] = (uint32_t)__popcll(e);
+    }
+  }
+  __syncthreads();
+  // scans over the chunks (a thread a run of consecutive chunks): ties before
+  // each chunk, then its first list position (the first `need` ties are taken)
+  const uint32_t per = (nch + T - 1) / T, c_lo = tid * per, c_hi = min(c_lo + per, nch);
+  uint32_t es = 0;
+  for (uint32_t c = c_lo; c < c_hi; ++c) es += ce[c];
+  uint32_t te = block_excl_scan(es, sh);
+  uint32_t ss = 0;
+  for (uint32_t c = c_lo; c < c_hi; ++c) {
+    const uint32_t sel = cg[c] + min(ce[c], need > te ? need - te : 0u);
+    te += ce[c];
+    ss += sel;
+  }
+  uint32_t pos = block_excl_scan(ss, sh);
+  const uint32_t total = block_sum(ss, &sh[4]);
+  te -= es;  // back to the ties before this thread's first chunk
+  for (uint32_t c = c_lo; c < c_hi; ++c) {
+    const uint32_t sel = cg[c] + min(ce[c], need > te ? need - te : 0u);
+    const uint32_t e0 = te;
+    te += ce[c];
+    cg[c] = pos;
+    ce[c] = e0;
+    pos += sel;
+  }
+  __syncthreads();
+  int32_t *jl = jlist_of(P, sig, loop);
+  uint32_t *jb = jbits_of(P, sig, loop);
+  for (uint32_t c = wave; c < nch; c += nw) {
+    const uint32_t b = (c << 6) + lane;
+    const R mb = m[b];
+    const bool eq = need > 0u && mb == v;
+    const unsigned long long e = __ballot(eq);
+    const bool f = mb > v || (eq && ce[c] + lanes_below(e) < need);
+    const unsigned long long fm = __ballot(f);
+    if (f) jl[cg[c] + lanes_below(fm)] = (int32_t)b;
+    if (lane == 0) {
+      jb[2 * c] = (uint32_t)fm;
+      jb[2 * c + 1] = (uint32_t)(fm >> 32);
+    }
+  }
+  if (tid == 0) jcount_of(P, sig)[loop] = (int32_t)total;
+}
+
 // -------------------------------------------------------------- k_vote ----
 
 constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x column preimages
@@ -1495,7 +1695,9 @@ constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x colu
 // and per column instead of two per pair.  SMALL: every hash product fits
 // 24-bit operands (1D n <= 2^24, and 2D), so the full-rate 24-bit multiply
 // gives the product modulo n.
-template <int NDIM, bool SMALL, bool DEV = false>
+// GB: the cutoff bitmaps are read from device memory (the L2) where they do
+// not fit in LDS (the large 2D bucket arrays).
+template <int NDIM, bool SMALL, bool DEV = false, bool GB = false>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   const KParams &P = params_of<DEV>(P0, blockIdx.z);
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
@@ -1529,10 +1731,14 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
     s_sig[threadIdx.x][1] = NDIM == 2 ? draw(P, sig, kPhaseLoc, it0 + (int)threadIdx.x, 1).sigma : 0u;
   }
   if (threadIdx.x == 0) s_qn = 0;
-  for (uint32_t i = threadIdx.x; i < L * words; i += blockDim.x) {
-    const uint32_t l = i / words, wi = i - l * words;
-    s_bits[i] = jbits_of(P, sig, l)[wi];
-  }
+  // the bitmaps: loop l's word i at bsrc[l * bstride + i]
+  const uint32_t *bsrc = GB ? jbits_of(P, sig, 0) : s_bits;
+  const uint32_t bstride = GB ? (uint32_t)(P.lay.jbits_loop / 4) : words;
+  if (!GB)
+    for (uint32_t i = threadIdx.x; i < L * words; i += blockDim.x) {
+      const uint32_t l = i / words, wi = i - l * words;
+      s_bits[i] = jbits_of(P, sig, l)[wi];
+    }
   __syncthreads();
   const int32_t *jl = jlist_of(P, sig, e);
   const uint32_t inv0 = inv_odd(s_sig[e][0]) & mask;
@@ -1551,7 +1757,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   };
   // the bit extract takes the bit index modulo 32 by itself
   auto in_J = [&](uint32_t l, uint32_t h) -> uint32_t {
-    return __builtin_amdgcn_ubfe(s_bits[l * words + (h >> 5)], h, 1u);
+    return __builtin_amdgcn_ubfe(bsrc[l * bstride + (h >> 5)], h, 1u);
   };
   // the m-th loop other than e
   auto other = [&](uint32_t m) -> uint32_t { return m < e ? m : m + 1u; };
@@ -1624,14 +1830,14 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
       if (logB >= 5u) {
         // a bitmap row is whole words: byte offsets of row h1's words and of
         // h2's word within a row, and h2's bit
-        const char *bits = reinterpret_cast<const char *>(s_bits);
+        const char *bits = reinterpret_cast<const char *>(bsrc);
         for (uint32_t m = 0; m < nA; ++m) {
           const uint32_t l = other(m);
           const uint32_t s1 = s_sig[l][0], s2 = s_sig[l][1];
           uint32_t r[KB], w2[KB], t2[KB];
 #pragma unroll
           for (uint32_t a = 0; a < KB; ++a) {
-            r[a] = (l * words + (axis(s1, f1[a]) << (logB - 5u))) << 2;
+            r[a] = (l * bstride + (axis(s1, f1[a]) << (logB - 5u))) << 2;
             t2[a] = axis(s2, f2[a]);
             w2[a] = (t2[a] >> 5) << 2;
           }
@@ -1652,7 +1858,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
           uint32_t r[KB], h2[KB];
 #pragma unroll
           for (uint32_t a = 0; a < KB; ++a) {
-            r[a] = ((l * words) << 5) + (axis(s1, f1[a]) << logB);
+            r[a] = ((l * bstride) << 5) + (axis(s1, f1[a]) << logB);
             h2[a] = axis(s2, f2[a]);
           }
 #pragma unroll
@@ -1660,7 +1866,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
 #pragma unroll
             for (uint32_t bb = 0; bb < KB; ++bb) {
               const uint32_t hb = r[a] + h2[bb];
-              v[a * KB + bb] += __builtin_amdgcn_ubfe(s_bits[hb >> 5], hb, 1u);
+              v[a * KB + bb] += __builtin_amdgcn_ubfe(bsrc[hb >> 5], hb, 1u);
             }
           }
         }
@@ -2360,6 +2566,18 @@ size_t residual_smem_bytes(int dtype, uint32_t Bc_max) {
 
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max) { return 4 * (size_t)L_loc * ((Bc_max + 31) / 32); }
 
+// LDS of the large-array kernels for B per axis (padded DFT buffers; the
+// cutoff's histograms, wave keys and two words per 64-bucket chunk)
+size_t big_rows_smem(int dtype, uint32_t B) {
+  const size_t cs = dtype == 0 ? 8 : 16;
+  return cs * (B + B / 32);
+}
+size_t big_cols_smem(int dtype, uint32_t B) {
+  const size_t cs = dtype == 0 ? 8 : 16, e = (size_t)B * (dtype == 0 ? 16 : 8);
+  return cs * (e + e / 32);
+}
+size_t big_stats_smem(uint32_t B) { return 4 * (512 + 32) + 8 * 2 * (kBucketThreads / 64) + 8 * ((size_t)B * B / 64); }
+
 size_t estimate_smem_bytes(uint32_t max_out) {
   uint32_t p2 = 1;
   while (p2 < max_out) p2 <<= 1;
@@ -2386,8 +2604,21 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
   if (e != hipSuccess) return e;
   for (const void *f : {reinterpret_cast<const void *>(&k_hash2d_stream<R, 4>),
                         reinterpret_cast<const void *>(&k_hash2d_stream<R, 8>),
-                        reinterpret_cast<const void *>(&k_hash2d_stream<R, 16>)}) {
+                        reinterpret_cast<const void *>(&k_hash2d_stream<R, 16>),
+                        reinterpret_cast<const void *>(&k_hash2d_stream<R, 4, kBucketThreads>)}) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowBytes);
+    if (e != hipSuccess) return e;
+  }
+  if (NDIM == 2) {
+    const int dt = sizeof(R) == 4 ? 0 : 1;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_big_rows<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)big_rows_smem(dt, kBigMax));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_big_cols<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)big_cols_smem(dt, kBigMax));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_big_stats<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)big_stats_smem(kBigMax));
     if (e != hipSuccess) return e;
   }
   for (const void *f : {reinterpret_cast<const void *>(&k_vote<NDIM, true>),
@@ -2475,36 +2706,55 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
   auto main_pass = [&](const KParams &Q0, bool marks) {
     KParams Q = Q0;
-    Q.rows2d = row_mode;
-    if (row_mode == 2) {
+    if (NDIM == 2 && Q.big) {
+      // large bucket arrays (fixed B): rows streamed once by 1024-thread
+      // workgroups, then the DFTs and the cutoffs in device memory
+      const uint32_t Bb = 1u << (ilog2_host_u32(P.Bc_max) / 2);
+      const int dt = sizeof(R) == 4 ? 0 : 1;
+      Q.rows2d = 2;
       const dim3 sgrid((P.n + P.stream_rows - 1) / P.stream_rows, batch);
-      const size_t rb = (size_t)P.n * sizeof(typename CT<R>::C);
-      if (rb <= 16u * 4u * kHashThreads)
-        hipLaunchKernelGGL((k_hash2d_stream<R, 4>), sgrid, dim3(kHashThreads), rb, s, Q);
-      else if (rb <= 16u * 8u * kHashThreads)
-        hipLaunchKernelGGL((k_hash2d_stream<R, 8>), sgrid, dim3(kHashThreads), rb, s, Q);
+      hipLaunchKernelGGL((k_hash2d_stream<R, 4, kBucketThreads>), sgrid, dim3(kBucketThreads),
+                         (size_t)P.n * sizeof(typename CT<R>::C), s, Q);
+      if (marks && mark) mark(ctx, 2);
+      hipLaunchKernelGGL((k_big_rows<R>), dim3(Bb, loops, batch), dim3(256), big_rows_smem(dt, Bb), s, Q);
+      hipLaunchKernelGGL((k_big_cols<R>), dim3(Bb / big_cols<R>(), loops, batch), dim3(256),
+                         big_cols_smem(dt, Bb), s, Q);
+      hipLaunchKernelGGL((k_big_stats<R>), dim3(P.L_loc, batch), dim3(kBucketThreads), big_stats_smem(Bb), s, Q);
+      if (marks && mark) mark(ctx, 3);
+      hipLaunchKernelGGL((k_vote<NDIM, true, DEV, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, Q);
+      if (marks && mark) mark(ctx, 4);
+    } else {
+      Q.rows2d = row_mode;
+      if (row_mode == 2) {
+        const dim3 sgrid((P.n + P.stream_rows - 1) / P.stream_rows, batch);
+        const size_t rb = (size_t)P.n * sizeof(typename CT<R>::C);
+        if (rb <= 16u * 4u * kHashThreads)
+          hipLaunchKernelGGL((k_hash2d_stream<R, 4>), sgrid, dim3(kHashThreads), rb, s, Q);
+        else if (rb <= 16u * 8u * kHashThreads)
+          hipLaunchKernelGGL((k_hash2d_stream<R, 8>), sgrid, dim3(kHashThreads), rb, s, Q);
+        else
+          hipLaunchKernelGGL((k_hash2d_stream<R, 16>), sgrid, dim3(kHashThreads), rb, s, Q);
+      }
+      else if (row_mode == 1)
+        hipLaunchKernelGGL((k_hash2d_rows<R>), dim3(1u << (ilog2_host_u32(P.Bc_max) / 2), loops, batch),
+                           dim3(kHashThreads), rows_smem, s, Q);
+      else if (sizeof(R) == 4 && Q.comp)
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, true, DEV>), hgrid1, dim3(kHashThreads), 0, s, Q, 0, 0);
+      else if (NDIM == 2 || LG == 1)
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
+      else if (LG == 2)
+        hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
       else
-        hipLaunchKernelGGL((k_hash2d_stream<R, 16>), sgrid, dim3(kHashThreads), rb, s, Q);
+        hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
+      if (marks && mark) mark(ctx, 2);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
+      if (marks && mark) mark(ctx, 3);
+      if (NDIM == 2 || P.logn <= 24)
+        hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+      else
+        hipLaunchKernelGGL((k_vote<NDIM, false, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
+      if (marks && mark) mark(ctx, 4);
     }
-    else if (row_mode == 1)
-      hipLaunchKernelGGL((k_hash2d_rows<R>), dim3(1u << (ilog2_host_u32(P.Bc_max) / 2), loops, batch),
-                         dim3(kHashThreads), rows_smem, s, Q);
-    else if (sizeof(R) == 4 && Q.comp)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, true, DEV>), hgrid1, dim3(kHashThreads), 0, s, Q, 0, 0);
-    else if (NDIM == 2 || LG == 1)
-      hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
-    else if (LG == 2)
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 2, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
-    else
-      hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
-    if (marks && mark) mark(ctx, 2);
-    hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
-    if (marks && mark) mark(ctx, 3);
-    if (NDIM == 2 || P.logn <= 24)
-      hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
-    else
-      hipLaunchKernelGGL((k_vote<NDIM, false, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
-    if (marks && mark) mark(ctx, 4);
     // estimate workgroups per signal: more for small batches, up to 32
     const uint32_t est_groups = std::min<uint32_t>(32u, std::max<uint32_t>((uint32_t)kEstGroups, 128u / (uint32_t)batch));
     if (Q.L_est <= 8)
