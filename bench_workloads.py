@@ -311,12 +311,14 @@ def _planted_error(r, plocs, pamps):
 
 def _compare_known_k(A, ndim, n, k, x, truth, args, seed):
     """Time ATSFFT and the known-k form on one batch; B_kk = sqrt(n k) per axis
-    rounded to a power of two and clipped to the plan's bucket cap."""
+    rounded to a power of two and clipped to the largest bucket count a plan
+    takes (1D: the plan's cap; 2D: 1024 per axis, the arrays then held in
+    device memory)."""
     import torch
 
     batch = x.shape[0]
     ada = A.Plan(ndim, n, "c64", seed=seed, max_batch=batch)
-    cap = ada.desc.B_max
+    cap = ada.desc.B_max if ndim == 1 else min(1024, n // 2)
     b_paper = int(round(np.log2(np.sqrt(float(n) * k))))
     B_kk = min(1 << b_paper, cap)
     kk = A.Plan(ndim, n, "c64", seed=seed, max_batch=batch, fixed_B=B_kk, fixed_k=k)
@@ -358,13 +360,27 @@ def run_known_k(args):
     img = [synth.make("c3_2d_c64_n4096_k256_snr30", 2000 + i) for i in range(8)]
     x = torch.from_numpy(np.stack([t[0] for t in img])).cuda()
     two = _compare_known_k(A, 2, 4096, 256, x, [(t[1], t[2]) for t in img], args, 7)
+    del x
+    # the paper's fixed-size sweep in kind (its Table 2): 2048^2 images, k
+    # planted frequencies of magnitude 1 and no noise, k = 50 .. 1000
+    sweep = []
+    for k in (50, 100, 200, 400, 800, 1000):
+        _log(f"2048^2 sweep: k = {k}")
+        img = [synth.planted_2d(2048, k, 9000 + 10 * k + i, dtype=np.complex64) for i in range(4)]
+        x = torch.from_numpy(np.stack([t[0] for t in img])).cuda()
+        r = _compare_known_k(A, 2, 2048, k, x, [(t[1], t[2]) for t in img], args, 7)
+        r["k"] = k
+        r["speedup"] = r["known_k"]["ms_per_transform"] / r["atsfft"]["ms_per_transform"]
+        sweep.append(r)
+        del x
     speed = one["known_k"]["ms_per_transform"] / one["atsfft"]["ms_per_transform"]
     line = _base("speedup of ATSFFT (k probed) over the known-k sparse FFT (B = sqrt(nk)), n=2^22 k=64",
                  speed, "x", args, one["atsfft"]["ms_per_transform"] * 16,
                  {"workload": "known_k_vs_atsfft", "1d": "16 x n=2^22 c64 k=64 40dB",
-                  "2d": "8 x 4096^2 c64 k=256 30dB"})
+                  "2d": "8 x 4096^2 c64 k=256 30dB", "2d_sweep": "4 x 2048^2 c64 |a|=1 no noise, k=50..1000"})
     line.update({"1d": one, "2d": two,
-                 "speedup_2d": two["known_k"]["ms_per_transform"] / two["atsfft"]["ms_per_transform"]})
+                 "speedup_2d": two["known_k"]["ms_per_transform"] / two["atsfft"]["ms_per_transform"],
+                 "2d_sweep": sweep})
     return line
 
 
