@@ -309,11 +309,12 @@ def _planted_error(r, plocs, pamps):
     return float(np.mean(hit)), float(e) / k
 
 
-def _compare_known_k(A, ndim, n, k, x, truth, args, seed):
+def _compare_known_k(A, ndim, n, k, x, truth, args, seed, wide=None):
     """Time ATSFFT and the known-k form on one batch; B_kk = sqrt(n k) per axis
     rounded to a power of two and clipped to the largest bucket count a plan
     takes (1D: the plan's cap; 2D: 1024 per axis, the arrays then held in
-    device memory)."""
+    device memory).  `wide`: knobs of a further ATSFFT plan (a B_max beyond
+    the default cap), timed as "atsfft_wide"."""
     import torch
 
     batch = x.shape[0]
@@ -323,7 +324,10 @@ def _compare_known_k(A, ndim, n, k, x, truth, args, seed):
     B_kk = min(1 << b_paper, cap)
     kk = A.Plan(ndim, n, "c64", seed=seed, max_batch=batch, fixed_B=B_kk, fixed_k=k)
     rows = {}
-    for name, plan in (("atsfft", ada), ("known_k", kk)):
+    plans = [("atsfft", ada), ("known_k", kk)]
+    if wide:
+        plans.append(("atsfft_wide", A.Plan(ndim, n, "c64", seed=seed, max_batch=batch, **wide)))
+    for name, plan in plans:
         out = plan.outputs(batch, x.device)
         ws = plan.workspace(batch, x.device)
         step = lambda: plan.execute_batched(x, out=out, ws=ws)
@@ -368,16 +372,18 @@ def run_known_k(args):
         _log(f"2048^2 sweep: k = {k}")
         img = [synth.planted_2d(2048, k, 9000 + 10 * k + i, dtype=np.complex64) for i in range(4)]
         x = torch.from_numpy(np.stack([t[0] for t in img])).cuda()
-        r = _compare_known_k(A, 2, 2048, k, x, [(t[1], t[2]) for t in img], args, 7)
+        r = _compare_known_k(A, 2, 2048, k, x, [(t[1], t[2]) for t in img], args, 7, wide={"B_max": 1024})
         r["k"] = k
         r["speedup"] = r["known_k"]["ms_per_transform"] / r["atsfft"]["ms_per_transform"]
+        r["speedup_wide"] = r["known_k"]["ms_per_transform"] / r["atsfft_wide"]["ms_per_transform"]
         sweep.append(r)
         del x
     speed = one["known_k"]["ms_per_transform"] / one["atsfft"]["ms_per_transform"]
     line = _base("speedup of ATSFFT (k probed) over the known-k sparse FFT (B = sqrt(nk)), n=2^22 k=64",
                  speed, "x", args, one["atsfft"]["ms_per_transform"] * 16,
                  {"workload": "known_k_vs_atsfft", "1d": "16 x n=2^22 c64 k=64 40dB",
-                  "2d": "8 x 4096^2 c64 k=256 30dB", "2d_sweep": "4 x 2048^2 c64 |a|=1 no noise, k=50..1000"})
+                  "2d": "8 x 4096^2 c64 k=256 30dB", "2d_sweep": "4 x 2048^2 c64 |a|=1 no noise, k=50..1000, "
+                               "ATSFFT at its default B_max (128) and at B_max = 1024"})
     line.update({"1d": one, "2d": two,
                  "speedup_2d": two["known_k"]["ms_per_transform"] / two["atsfft"]["ms_per_transform"],
                  "2d_sweep": sweep})

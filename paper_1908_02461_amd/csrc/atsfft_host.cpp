@@ -22,7 +22,8 @@ struct atsfft_plan_s {
   int device;
   uint32_t logn;
   uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
-  uint32_t big;      // 2D fixed-B arrays above the LDS-resident size: DFTs and cutoffs in device memory
+  uint32_t big;      // 2D arrays above the LDS-resident size: DFTs and cutoffs in device memory
+  uint32_t lds_cap;  // largest bucket array (B^ndim) k_bucket holds in LDS
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t tab_host[128];  // element offsets by log2 B (passed in the kernel arguments)
@@ -74,7 +75,6 @@ namespace {
 
 thread_local std::string g_err = "";
 constexpr size_t kMaxGraphs = 64;  // call shapes kept per plan under ATSFFT_FLAG_GRAPH
-constexpr uint32_t kBigStandIn = 4096;  // bucket count whose LDS sizes a large-array plan's unused kernels
 
 atsfft_status fail(atsfft_status s, const std::string &msg) {
   g_err = msg;
@@ -168,8 +168,8 @@ atsfft_status validate(const atsfft_desc *d) {
     return fail(ATSFFT_EINVAL, "the residual test needs B_max a power of two in [2, n/2] (2D: [4, N/2])");
   const int64_t Bbig = main_bmax(d);
   const int64_t Bc = d->ndim == 1 ? Bbig : Bbig * Bbig;
-  if (Bc > (int64_t)kBucketThreads * kBucketMaxPer && !(d->ndim == 2 && fixed && Bbig <= (int64_t)kBigMax))
-    return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384 (2D with FIXED_B: B <= 1024)");
+  if (Bc > (int64_t)kBucketThreads * kBucketMaxPer && !(d->ndim == 2 && Bbig <= (int64_t)kBigMax))
+    return fail(ATSFFT_EINVAL, "largest bucket array B^ndim must be <= 16384 (2D: B <= 1024)");
   if (d->alpha < 2 || d->alpha > 1024 || (d->alpha & 1)) return fail(ATSFFT_EINVAL, "alpha must be even in [2, 1024]");
   if (d->L_loc < 1 || d->L_loc > kMaxLoops - 1) return fail(ATSFFT_EINVAL, "L_loc must be in [1, 31]");
   if (d->L_est < 1 || d->L_est > kMaxLoops - 1 || (d->L_est % 2) == 0)
@@ -318,6 +318,7 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.pass = 0;
   P.comp = (d.flags & ATSFFT_FLAG_COMPENSATED) && d.dtype == ATSFFT_C64 ? 1u : 0u;
   P.big = plan->big;
+  P.lds_cap = plan->lds_cap;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;
@@ -546,13 +547,15 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   }
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
   p->big = 0;
+  p->lds_cap = p->Bc_max;
   if (p->bucket_smem > prop.sharedMemPerBlock) {
-    // 2D with a fixed B (the known-k form at the sparse FFT's bucket count):
-    // the bucket arrays live in device memory; needs rows streamed once
-    // (a row fits the row buffer, w / B <= kSlabs partials) and no probe,
-    // residual test, compensated fold, uneven lengths or adjoint
+    // 2D arrays above the LDS size (the known-k form at the sparse FFT's
+    // bucket count, or a B_max beyond it): those arrays live in device
+    // memory; needs rows streamed once (a row fits the row buffer, w / B <=
+    // kSlabs partials) and no residual test, compensated fold, uneven
+    // lengths or adjoint
     const uint64_t row_bytes = (uint64_t)n * (d->dtype == ATSFFT_C64 ? 8 : 16);
-    const bool big_ok = d->ndim == 2 && fixed && d->res_tol == 0.0 && d->n_min == 0 &&
+    const bool big_ok = d->ndim == 2 && d->res_tol == 0.0 && d->n_min == 0 &&
                         !(d->flags & ATSFFT_FLAG_COMPENSATED) && Bbig <= (int64_t)kBigMax &&
                         d->alpha <= kSlabs && row_bytes <= kRowBytes &&
                         big_cols_smem(d->dtype, (uint32_t)Bbig) <= prop.sharedMemPerBlock &&
@@ -560,18 +563,24 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     if (!big_ok) {
       char msg[200];
       std::snprintf(msg, sizeof(msg),
-                    "B_max^ndim = %u needs %zu bytes of LDS, device has %zu (larger arrays: 2D, FIXED_B, "
+                    "B_max^ndim = %u needs %zu bytes of LDS, device has %zu (larger arrays: 2D, "
                     "B <= %u, alpha <= 8, no residual test, compensation or uneven lengths)",
                     p->Bc_max, p->bucket_smem, (size_t)prop.sharedMemPerBlock, kBigMax);
       free_plan(p);
       return fail(ATSFFT_EINVAL, msg);
     }
     p->big = 1;
-    // k_bucket and the adjoint do not run on such a plan; their LDS settings
-    // are those of a small array (kBigStandIn buckets), within the device's
-    p->bucket_smem = bucket_smem_bytes(d->dtype, kBigStandIn);
+    // the largest B x B array k_bucket still holds in LDS takes the smaller
+    // ones (probe levels, signals whose B_star is small); the adjoint does
+    // not run on such a plan
+    while (p->lds_cap > 16 && (p->lds_cap > kBucketThreads * kBucketMaxPer ||
+                               bucket_smem_bytes(d->dtype, p->lds_cap) > prop.sharedMemPerBlock))
+      p->lds_cap /= 4;
+    p->bucket_smem = bucket_smem_bytes(d->dtype, p->lds_cap);
+    // the 2D main-loop hash streams rows (one partial per row wrap)
+    p->rows2d_ok = 2;
   }
-  p->bwd_smem = bwd_smem_bytes(d->dtype, p->big ? kBigStandIn : p->Bc_max, (uint32_t)d->max_out);
+  p->bwd_smem = bwd_smem_bytes(d->dtype, p->big ? p->lds_cap : p->Bc_max, (uint32_t)d->max_out);
 
   // window tables for every bucket count a loop may use
   std::vector<double> taps_all, ghat_all;

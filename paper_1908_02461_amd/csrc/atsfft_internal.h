@@ -104,6 +104,7 @@ struct KParams {
   uint32_t pass;         // the pass this launch runs (signals of other passes skip)
   uint32_t comp;         // FP32 fold sums compensated (Neumaier), slab partials added in FP64
   uint32_t big;          // 2D bucket arrays above the LDS-resident size: DFTs and cutoffs in device memory
+  uint32_t lds_cap;      // largest bucket array (B^ndim) k_bucket holds in LDS
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
   int64_t tab[128];    // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),

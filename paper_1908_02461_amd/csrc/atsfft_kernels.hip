@@ -940,6 +940,8 @@ __global__ __launch_bounds__(NT) void k_hash2d_stream(KParams P) {
   const SigState st = *state_of(P, sig);
   if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
   const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
+  // arrays above the LDS size are hashed by the 1024-thread instantiation
+  if (P.big && ((size_t)B * B > (size_t)P.lds_cap) != (NT == kBucketThreads)) return;
   const uint32_t n = P.n, mask = n - 1u;
   const uint32_t w = min(P.alpha * B, n), half = w >> 1, wraps = w >> logB;
   const uint32_t nloops = P.L_loc + P.L_est;
@@ -1156,6 +1158,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   }
   const uint32_t logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
+  if (Bc > P.lds_cap) return;  // a large array: k_big_rows, k_big_cols, k_big_stats
   const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
   const uint32_t tid = threadIdx.x, T = blockDim.x;
 
@@ -1488,34 +1491,72 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
 
 // ------------------------------------------------ large 2D bucket arrays ----
 
-// 2D bucket arrays above the LDS-resident size (B x B > kBucketThreads *
-// kBucketMaxPer, up to 1024 x 1024; the known-k form at the sparse FFT's
-// bucket count, B = sqrt(N k) per axis) are transformed and cut in device
-// memory: k_big_rows adds a bucket row's row-wrap partials and takes its
-// B-point DFT along b2, k_big_cols takes the B-point DFTs along b1 of a block
-// of kBigCols columns, and k_big_stats (location loops) computes m = |y|^2,
-// the noise floor, T and the top-num cutoff J with the selects run over
-// device memory.  The results sit where k_bucket leaves them (y_hat in the
-// first partial slot, m in the second as scratch, J as bitmap and list).
+// 2D bucket arrays above the LDS-resident size (B x B > lds_cap, up to
+// 1024 x 1024: the known-k form at the sparse FFT's bucket count, B =
+// sqrt(N k) per axis, and probe levels and main loops of plans whose B_max
+// goes beyond the LDS) are transformed and cut in device memory: k_big_rows
+// adds a bucket row's row-wrap partials and takes its B-point DFT along b2,
+// k_big_cols takes the B-point DFTs along b1 of a block of big_cols()
+// columns, and k_big_stats computes m = |y|^2, the noise floor and T, then
+// either the top-num cutoff J (location loops) or the local-maximum count
+// and the B-update rule (probe levels), with the selects over device
+// memory.  The results sit where k_bucket leaves them (y_hat in the first
+// partial slot, m in a spare one, J as bitmap and list).  The in-LDS kernels
+// skip such arrays and these kernels skip the others, so a batch may mix them.
 
-// one workgroup per (bucket row b1, loop, signal)
+// The array a large-array kernel works on: role 0 main loop `idx` (its
+// row-wrap partials at stride Bc_max, m written into the second), role 1
+// probe level `idx` (one partial; m written after it).  `ok` is false when
+// the signal does not run it here (finished, beyond its levels, or an array
+// that k_bucket holds in LDS).
+template <typename C> struct BigArr {
+  C *y;
+  uint32_t B, parts;
+  size_t pstride;
+  bool ok;
+};
+template <typename C>
+__device__ __forceinline__ BigArr<C> big_arr(const KParams &P, uint32_t sig, int role, uint32_t idx) {
+  BigArr<C> a;
+  a.ok = false;
+  a.y = nullptr;
+  a.B = 0;
+  a.parts = 0;
+  a.pstride = 0;
+  const SigState *st = state_of(P, sig);
+  if (role == 0) {
+    if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return a;
+    a.B = (uint32_t)st->B_star;
+    a.y = ymain_of<C>(P, sig, idx);
+    a.parts = min(P.alpha * a.B, P.n) >> ilog2(a.B);
+    a.pstride = P.Bc_max;
+  } else {
+    if (st->done || idx >= P.probe_levels) return a;
+    a.B = P.B0 << idx;
+    a.y = yprobe_of<C>(P, sig, idx);
+    a.parts = 1;
+    a.pstride = (size_t)a.B * a.B;
+  }
+  a.ok = (size_t)a.B * a.B > (size_t)P.lds_cap;
+  return a;
+}
+
+// one workgroup per (bucket row b1, loop or level, signal)
 template <typename R>
-__global__ __launch_bounds__(256) void k_big_rows(KParams P) {
+__global__ __launch_bounds__(256) void k_big_rows(KParams P, int role, int iter) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   C *buf = reinterpret_cast<C *>(smem);
-  const uint32_t b1 = blockIdx.x, loop = blockIdx.y, sig = blockIdx.z;
-  const SigState st = *state_of(P, sig);
-  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
-  const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
-  if (b1 >= B) return;
-  const uint32_t wraps = min(P.alpha * B, P.n) >> logB;
-  C *y = ymain_of<C>(P, sig, loop);
+  const uint32_t b1 = blockIdx.x, sig = blockIdx.z;
+  const BigArr<C> ar = big_arr<C>(P, sig, role, (uint32_t)iter + blockIdx.y);
+  if (!ar.ok || b1 >= ar.B) return;
+  const uint32_t B = ar.B, logB = ilog2(B);
+  C *y = ar.y;
   const size_t row = (size_t)b1 << logB;
   for (uint32_t b2 = threadIdx.x; b2 < B; b2 += blockDim.x) {
     C v = y[row + b2];
-    for (uint32_t r = 1; r < wraps; ++r) {
-      const C u = y[(size_t)r * P.Bc_max + row + b2];
+    for (uint32_t r = 1; r < ar.parts; ++r) {
+      const C u = y[(size_t)r * ar.pstride + row + b2];
       v.x += u.x;
       v.y += u.y;
     }
@@ -1528,20 +1569,19 @@ __global__ __launch_bounds__(256) void k_big_rows(KParams P) {
 
 template <typename R> constexpr uint32_t big_cols() { return sizeof(R) == 4 ? 16u : 8u; }
 
-// one workgroup per (block of big_cols() columns, loop, signal)
+// one workgroup per (block of big_cols() columns, loop or level, signal)
 template <typename R>
-__global__ __launch_bounds__(256) void k_big_cols(KParams P) {
+__global__ __launch_bounds__(256) void k_big_cols(KParams P, int role, int iter) {
   using C = typename CT<R>::C;
   constexpr uint32_t CB = big_cols<R>();
   extern __shared__ __align__(16) unsigned char smem[];
   C *buf = reinterpret_cast<C *>(smem);
-  const uint32_t loop = blockIdx.y, sig = blockIdx.z;
-  const SigState st = *state_of(P, sig);
-  if ((st.status & kSigEmpty) || st.pass != (int32_t)P.pass) return;
-  const uint32_t B = (uint32_t)st.B_star, logB = ilog2(B);
+  const uint32_t sig = blockIdx.z;
+  const BigArr<C> ar = big_arr<C>(P, sig, role, (uint32_t)iter + blockIdx.y);
   const uint32_t c0 = blockIdx.x * CB;
-  if (c0 >= B) return;
-  C *y = ymain_of<C>(P, sig, loop);
+  if (!ar.ok || c0 >= ar.B) return;
+  const uint32_t B = ar.B, logB = ilog2(B);
+  C *y = ar.y;
   for (uint32_t i = threadIdx.x; i < B * CB; i += blockDim.x) {
     const uint32_t b1 = i / CB, c = i % CB;
     buf[lds_at<true>(bitrev(b1, logB) * CB + c)] = y[((size_t)b1 << logB) + c0 + c];
@@ -1554,10 +1594,11 @@ __global__ __launch_bounds__(256) void k_big_cols(KParams P) {
   }
 }
 
-// one 1024-thread workgroup per (location loop, signal): the same threshold
-// and cutoff as k_bucket's location role, over device memory
+// one 1024-thread workgroup per (location loop or probe level, signal): the
+// threshold of k_bucket, then (role 0) its top-num cutoff or (role 1) its
+// local-maximum count and the B-update rule for the level, over device memory
 template <typename R>
-__global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
+__global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int role, int iter) {
   using C = typename CT<R>::C;
   using K = typename CT<R>::K;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1565,15 +1606,16 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
   uint32_t *sh = hist + 512;                             // 32 words
   K *wk = reinterpret_cast<K *>(sh + 32);                // 2 keys per wave
   uint32_t *cg = reinterpret_cast<uint32_t *>(wk + 2 * (kBucketThreads / 64));  // per-chunk counts
-  const uint32_t loop = blockIdx.x, sig = blockIdx.y;
+  const uint32_t idx = (uint32_t)iter + blockIdx.x, sig = blockIdx.y;
+  const BigArr<C> ar = big_arr<C>(P, sig, role, idx);
+  if (!ar.ok) return;
   SigState *st = state_of(P, sig);
-  if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
-  const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
+  const uint32_t B = ar.B, logB = ilog2(B);
   const uint32_t Bc = B * B, nch = Bc >> 6;
   uint32_t *ce = cg + nch;
   const uint32_t tid = threadIdx.x, T = blockDim.x, lane = tid & 63u, wave = tid >> 6, nw = T >> 6;
-  C *y = ymain_of<C>(P, sig, loop);
-  R *m = reinterpret_cast<R *>(y + P.Bc_max);  // the second partial slot, free after k_big_rows
+  const C *y = ar.y;
+  R *m = reinterpret_cast<R *>(ar.y + (role == 0 ? (size_t)P.Bc_max : (size_t)Bc));  // a spare partial slot
   K kmax = 0, kmin = ~(K)0;
   for (uint32_t b = tid; b < Bc; b += T) {
     const C v = y[b];
@@ -1605,7 +1647,38 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
   const double t2 = P.rho * (double)mmax;
   const double Td = t1 > t2 ? t1 : t2;
   const R Tr = (R)Td;
-  if (tid == 0) tloc_of(P, sig)[loop] = Td;
+
+  if (role == 1) {
+    // local maxima among significant buckets, the 8-neighbourhood on the
+    // torus, strict on the key (m, -index)
+    uint32_t c = 0;
+    for (uint32_t b = tid; b < Bc; b += T) {
+      if (!(m[b] > Tr)) continue;
+      const uint32_t r = b >> logB, q = b & (B - 1u);
+      bool is_max = true;
+      for (int dr = -1; dr <= 1; ++dr)
+        for (int dq = -1; dq <= 1; ++dq) {
+          if (dr == 0 && dq == 0) continue;
+          const uint32_t nb = (((r + (uint32_t)dr) & (B - 1u)) << logB) | ((q + (uint32_t)dq) & (B - 1u));
+          is_max = is_max && key_gt(m, b, nb);
+        }
+      c += is_max ? 1u : 0u;
+    }
+    const uint32_t k = block_sum(c, &sh[4]);
+    if (tid == 0) {
+      ProbeRec *h = hist_of(P, sig) + idx;
+      h->B = (int32_t)B;
+      h->dec = 0;
+      h->T = Td;
+      if ((int32_t)idx != P.probe_drop)
+        __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // a large level is a round of its own: this workgroup applies the rule
+      probe_control<2>(P, sig, (int)idx, (int)idx + 1);
+    }
+    return;
+  }
+
+  if (tid == 0) tloc_of(P, sig)[idx] = Td;
   uint32_t above = 0;
   for (uint32_t b = tid; b < Bc; b += T) above += m[b] > Tr ? 1u : 0u;
   const uint32_t n_above = block_sum(above, &sh[4]);
@@ -1654,8 +1727,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
     pos += sel;
   }
   __syncthreads();
-  int32_t *jl = jlist_of(P, sig, loop);
-  uint32_t *jb = jbits_of(P, sig, loop);
+  int32_t *jl = jlist_of(P, sig, idx);
+  uint32_t *jb = jbits_of(P, sig, idx);
   for (uint32_t c = wave; c < nch; c += nw) {
     const uint32_t b = (c << 6) + lane;
     const R mb = m[b];
@@ -1669,7 +1742,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P) {
       jb[2 * c + 1] = (uint32_t)(fm >> 32);
     }
   }
-  if (tid == 0) jcount_of(P, sig)[loop] = (int32_t)total;
+  if (tid == 0) jcount_of(P, sig)[idx] = (int32_t)total;
 }
 
 // -------------------------------------------------------------- k_vote ----
@@ -1715,6 +1788,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
   const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
+  if ((Bc > P.lds_cap) != GB) return;  // bitmaps in LDS, or (GB) of the large arrays in device memory
   const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
   // workgroup work items: selected buckets, or in 2D rounds of KB x KB blocks
@@ -2653,7 +2727,7 @@ static uint32_t ilog2_host_u32(uint32_t v) {
 
 template <typename R, int NDIM, bool DEV = false>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
-  const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, P.Bc_max);
+  const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, min(P.Bc_max, P.lds_cap));
   const size_t esmem = estimate_smem_bytes(P.max_out);
   const uint32_t hash_blocks = kSlabs * max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
@@ -2662,11 +2736,32 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     // rounds of probe levels: every level up to B = probe_first at once, then
     // probe_step levels per round
     uint32_t lo = 0;
+    auto level_bc = [&](uint32_t l) -> uint64_t {
+      const uint64_t Bl = (uint64_t)P.B0 << l;
+      return NDIM == 1 ? Bl : Bl * Bl;
+    };
     while (lo < P.probe_levels) {
+      if (NDIM == 2 && level_bc(lo) > P.lds_cap) {
+        // a level above the LDS size is a round of its own: hashed, then its
+        // DFT, threshold, local maxima and B-update rule in device memory
+        const uint32_t Bl = P.B0 << lo;
+        const int dt = sizeof(R) == 4 ? 0 : 1;
+        const uint32_t slots = max(1u, min(P.tile_slots, (Bl * Bl + kTile - 1) / kTile));
+        hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(slots, 1, batch), dim3(kHashThreads), 0, s,
+                           P, (int)lo, (int)lo + 1);
+        hipLaunchKernelGGL((k_big_rows<R>), dim3(Bl, 1, batch), dim3(256), big_rows_smem(dt, Bl), s, P, 1, (int)lo);
+        hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bl / big_cols<R>()), 1, batch), dim3(256),
+                           big_cols_smem(dt, Bl), s, P, 1, (int)lo);
+        hipLaunchKernelGGL((k_big_stats<R>), dim3(1, batch), dim3(kBucketThreads), big_stats_smem(Bl), s, P, 1,
+                           (int)lo);
+        ++lo;
+        continue;
+      }
       uint32_t hi = lo == 0 ? 1 : lo + P.probe_step;
       if (lo == 0)
         while (hi < P.probe_levels && (P.B0 << hi) <= P.probe_first) ++hi;
       hi = min(hi, P.probe_levels);
+      while (hi > lo + 1 && level_bc(hi - 1) > P.lds_cap) --hi;  // k_bucket rounds hold LDS-sized levels only
       // (level, slot) pairs: each level as many slots as it has tiles, at
       // most tile_slots (so that small levels launch no idle workgroups)
       uint32_t slots = 0;
@@ -2707,21 +2802,32 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   auto main_pass = [&](const KParams &Q0, bool marks) {
     KParams Q = Q0;
     if (NDIM == 2 && Q.big) {
-      // large bucket arrays (fixed B): rows streamed once by 1024-thread
-      // workgroups, then the DFTs and the cutoffs in device memory
+      // arrays above the LDS size (this branch) and the others (the usual
+      // launches below) each skip the other kind, so a batch may hold both:
+      // rows streamed once, by 1024-thread workgroups for the large arrays,
+      // then their DFTs and cutoffs in device memory
       const uint32_t Bb = 1u << (ilog2_host_u32(P.Bc_max) / 2);
       const int dt = sizeof(R) == 4 ? 0 : 1;
       Q.rows2d = 2;
       const dim3 sgrid((P.n + P.stream_rows - 1) / P.stream_rows, batch);
-      hipLaunchKernelGGL((k_hash2d_stream<R, 4, kBucketThreads>), sgrid, dim3(kBucketThreads),
-                         (size_t)P.n * sizeof(typename CT<R>::C), s, Q);
+      const size_t rb = (size_t)P.n * sizeof(typename CT<R>::C);
+      hipLaunchKernelGGL((k_hash2d_stream<R, 4, kBucketThreads>), sgrid, dim3(kBucketThreads), rb, s, Q);
+      if (rb <= 16u * 4u * kHashThreads)
+        hipLaunchKernelGGL((k_hash2d_stream<R, 4>), sgrid, dim3(kHashThreads), rb, s, Q);
+      else if (rb <= 16u * 8u * kHashThreads)
+        hipLaunchKernelGGL((k_hash2d_stream<R, 8>), sgrid, dim3(kHashThreads), rb, s, Q);
+      else
+        hipLaunchKernelGGL((k_hash2d_stream<R, 16>), sgrid, dim3(kHashThreads), rb, s, Q);
       if (marks && mark) mark(ctx, 2);
-      hipLaunchKernelGGL((k_big_rows<R>), dim3(Bb, loops, batch), dim3(256), big_rows_smem(dt, Bb), s, Q);
-      hipLaunchKernelGGL((k_big_cols<R>), dim3(Bb / big_cols<R>(), loops, batch), dim3(256),
-                         big_cols_smem(dt, Bb), s, Q);
-      hipLaunchKernelGGL((k_big_stats<R>), dim3(P.L_loc, batch), dim3(kBucketThreads), big_stats_smem(Bb), s, Q);
+      hipLaunchKernelGGL((k_big_rows<R>), dim3(Bb, loops, batch), dim3(256), big_rows_smem(dt, Bb), s, Q, 0, 0);
+      hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bb / big_cols<R>()), loops, batch), dim3(256),
+                         big_cols_smem(dt, Bb), s, Q, 0, 0);
+      hipLaunchKernelGGL((k_big_stats<R>), dim3(P.L_loc, batch), dim3(kBucketThreads), big_stats_smem(Bb), s, Q, 0, 0);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
       if (marks && mark) mark(ctx, 3);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, Q);
+      hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads),
+                         vote_smem_bytes(P.L_loc, P.lds_cap), s, Q);
       if (marks && mark) mark(ctx, 4);
     } else {
       Q.rows2d = row_mode;
