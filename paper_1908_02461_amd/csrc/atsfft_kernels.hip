@@ -174,20 +174,50 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t v, uint32_t bits) {
 
 // ------------------------------------------------------- block helpers ----
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Wave-level primitives on the DPP crossbar (every lane of the wave active):
+// shifts within rows of 16 lanes, then the row totals broadcast into the rows
+// above, a handful of VALU operations instead of LDS permutes.  `old` is the
+// value a lane without a source lane takes (the identity of the operation).
+template <int CTRL, int ROWS = 0xF> __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+// Inclusive prefix sum over the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += dpp<0x111>(0u, v);  // row_shr:1
+  v += dpp<0x112>(0u, v);  // row_shr:2
+  v += dpp<0x114>(0u, v);  // row_shr:4
+  v += dpp<0x118>(0u, v);  // row_shr:8
+  v += dpp<0x142, 0xA>(0u, v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(0u, v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
-  return v;
+// Sum over the wave, uniform.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return lane_value(wave_incl_scan(v), 63); }
+
+// 64-bit values: both halves moved alike
+template <int CTRL, int ROWS = 0xF> __device__ __forceinline__ unsigned long long dpp(uint32_t old, unsigned long long v) {
+  return ((unsigned long long)dpp<CTRL, ROWS>(old, (uint32_t)(v >> 32)) << 32) | dpp<CTRL, ROWS>(old, (uint32_t)v);
+}
+__device__ __forceinline__ unsigned long long lane_value(unsigned long long v, uint32_t lane) {
+  return ((unsigned long long)lane_value((uint32_t)(v >> 32), lane) << 32) | lane_value((uint32_t)v, lane);
+}
+
+// Largest (MAX) or smallest key over the wave, uniform.
+template <bool MAX, typename K> __device__ __forceinline__ K wave_extreme(K v) {
+  const uint32_t id = MAX ? 0u : ~0u;  // per 32-bit half
+  auto op = [](K a, K b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+  v = op(v, dpp<0x111>(id, v));
+  v = op(v, dpp<0x112>(id, v));
+  v = op(v, dpp<0x114>(id, v));
+  v = op(v, dpp<0x118>(id, v));
+  v = op(v, dpp<0x142, 0xA>(id, v));
+  v = op(v, dpp<0x143, 0xC>(id, v));
+  return lane_value(v, 63);
 }
 
 // Set bits of a wave mask in the lanes below this one.
@@ -195,49 +225,107 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Sum over the block; `sh` is one LDS word.  Every thread gets the total.
+// Sum over the block; `sh` holds one LDS word per wave.  Every thread gets
+// the total.
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
-  if (threadIdx.x == 0) *sh = 0;
-  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) atomicAdd(sh, v);
+  if (lane == 0) sh[wave] = v;
   __syncthreads();
-  uint32_t r = *sh;
+  const uint32_t r = wave_sum(lane < nw ? sh[lane] : 0u);
   __syncthreads();
   return r;
 }
 
-// Exclusive prefix sum over the block in thread order; `sh` holds one word per
-// wave, from word 8 on (words 0..7 are left to the callers' other uses).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh) {
+// Exclusive prefix sum over the block in thread order, and the block total;
+// `sh` holds one word per wave, from word 8 on (words 0..7 are left to the
+// callers' other uses).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total = nullptr) {
+  const uint32_t lane = threadIdx.x & 63u, nw = (blockDim.x + 63) >> 6;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t incl = wave_incl_scan(v);
-  const uint32_t wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  if ((threadIdx.x & 63) == 63) sh[8 + wave] = incl;
+  if (lane == 63) sh[8 + wave] = incl;
   __syncthreads();
-  uint32_t before = 0;
-  for (uint32_t w = 0; w < wave; ++w) before += sh[8 + w];
-  (void)nw;
+  const uint32_t waves = wave_incl_scan(lane < nw ? sh[8 + lane] : 0u);
+  const uint32_t before = wave ? lane_value(waves, wave - 1) : 0u;
+  if (total) *total = lane_value(waves, nw - 1);
   __syncthreads();
   return before + incl - v;
 }
 
-// The k-th smallest (0-based) of the values of m[0..cnt) (in LDS or device
-// memory) that exceed `above` (default: all), by most-significant-digit radix selection on the
-// bit patterns (the values are non-negative, so their patterns order like the
-// values).  When the keys' range [lo, hi] is known, the digits are taken of
-// key - lo from the top bit of hi - lo, so that the first pass spreads the
-// keys over all 256 bins instead of the few that the exponent's top bits
-// give.  `hist` has 2 x 256 words, used in turn so
-// that each pass clears the next pass's histogram while it counts; `sh` has 4
-// words (the chosen digit and rank, also in turn).
+// The k-th smallest (0-based) of a block's values that exceed `above`
+// (default: all non-negative ones), by most-significant-digit radix selection
+// on the bit patterns (the values are non-negative, so their patterns order
+// like the values; negative ones mark empty slots).  `for_each(f)` calls f on
+// each of the calling thread's values.
+// When the keys' range [lo, hi] is known, the digits are taken of key - lo
+// from the top bit of hi - lo, so that the first pass spreads the keys over
+// all 256 bins instead of the few that the exponent's top bits give.  `hist`
+// has 2 x 256 words, used in turn so that each pass clears the next pass's
+// histogram while it counts; `sh` has 4 words (the chosen digit and rank,
+// also in turn).
 __device__ __forceinline__ int bit_length(uint32_t v) { return v ? 32 - __clz((int)v) : 0; }
 __device__ __forceinline__ int bit_length(unsigned long long v) { return v ? 64 - __clzll((long long)v) : 0; }
 
-template <typename R>
-__device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
-                                                uint32_t *sh, R above = (R)-1,
-                                                typename CT<R>::K lo = 0,
-                                                typename CT<R>::K hi = ~(typename CT<R>::K)0) {
+// A thread's run of equal digits in a digit pass, added with one atomic
+// (leading digits are shared by many values, and same-address atomics
+// serialise)
+struct DigitRun {
+  uint32_t bin, run;
+};
+__device__ __forceinline__ void digit_add(DigitRun &r, uint32_t *h, uint32_t bin, bool take) {
+  // selects rather than branches: only the atomic is predicated
+  const bool flush = take && r.run != 0u && bin != r.bin;
+  if (flush) atomicAdd(&h[r.bin], r.run);
+  r.run = take ? (flush ? 1u : r.run + 1u) : r.run;
+  r.bin = take ? bin : r.bin;
+}
+__device__ __forceinline__ void digit_flush(const DigitRun &r, uint32_t *h) {
+  if (r.run) atomicAdd(&h[r.bin], r.run);
+}
+
+// After a pass's histogram h is complete: one wave finds the digit whose bin
+// holds rank k and writes it and the rank within the bin to out[0], out[1].
+__device__ __forceinline__ void digit_pick(const uint32_t *h, uint32_t k, uint32_t *out) {
+  const uint32_t l = threadIdx.x & 63u;
+  const uint4 c = *reinterpret_cast<const uint4 *>(h + 4 * l);  // h 16-byte aligned
+  const uint32_t c0 = c.x, c1 = c.y, c2 = c.z, c3 = c.w;
+  const uint32_t s = c0 + c1 + c2 + c3;
+  const uint32_t incl = wave_incl_scan(s);
+  const uint32_t excl = incl - s;
+  if (excl <= k && k < incl) {
+    uint32_t digit, run;
+    if (k < excl + c0) {
+      digit = 4 * l;
+      run = excl;
+    } else if (k < excl + c0 + c1) {
+      digit = 4 * l + 1;
+      run = excl + c0;
+    } else if (k < excl + c0 + c1 + c2) {
+      digit = 4 * l + 2;
+      run = excl + c0 + c1;
+    } else {
+      digit = 4 * l + 3;
+      run = excl + c0 + c1 + c2;
+    }
+    out[0] = digit;
+    out[1] = k - run;
+  }
+}
+
+// The values a select reads: thread t's v[j], j < per (REGS; uniform over
+// the block, negative where the thread has no value), or m[t + i blockDim.x]
+// below cnt.
+template <typename R, int NPER, bool REGS> struct SelSrc {
+  const R (&v)[NPER];
+  uint32_t per;
+  const R *m;
+  uint32_t cnt;
+};
+
+template <typename R, int NPER, bool REGS>
+__device__ __forceinline__ R radix_select(const SelSrc<R, NPER, REGS> &src, uint32_t k, uint32_t *hist,
+                                          uint32_t *sh, R above, typename CT<R>::K lo, typename CT<R>::K hi) {
   using K = typename CT<R>::K;
   const int nbits = hi > lo ? bit_length(hi - lo) : 1;
   K prefix = 0, mask = 0;
@@ -252,51 +340,30 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
     uint32_t *h = hist + 256 * (pass & 1);
     uint32_t *hn = hist + 256 * ((pass + 1) & 1);
     uint32_t *out = sh + 2 * (pass & 1);
-    // a thread adds runs of equal digits in one atomic: the leading digits
-    // are shared by many values, and same-address atomics serialise
-    uint32_t run_bin = 0, run = 0;
-    for (uint32_t b = threadIdx.x; b < cnt; b += blockDim.x) {
-      const R mb = m[b];
-      const K key = key_of(mb) - lo;
-      if ((key & mask) == prefix && (above < (R)0 || mb > above)) {
-        const uint32_t bin = (uint32_t)(key >> shift) & dmask;
-        if (run && bin != run_bin) {
-          atomicAdd(&h[run_bin], run);
-          run = 0;
+    DigitRun r = {0, 0};
+    if constexpr (REGS) {
+#pragma unroll
+      for (int j = 0; j < NPER; ++j) {
+        if ((uint32_t)j < src.per) {
+          const R mb = src.v[j];
+          const K key = key_of(mb) - lo;
+          digit_add(r, h, (uint32_t)(key >> shift) & dmask,
+                    (key & mask) == prefix && (above < (R)0 ? mb >= (R)0 : mb > above));
         }
-        run_bin = bin;
-        ++run;
+      }
+    } else {
+      for (uint32_t b = threadIdx.x; b < src.cnt; b += blockDim.x) {
+        const R mb = src.m[b];
+        const K key = key_of(mb) - lo;
+        digit_add(r, h, (uint32_t)(key >> shift) & dmask,
+                  (key & mask) == prefix && (above < (R)0 ? mb >= (R)0 : mb > above));
       }
     }
-    if (run) atomicAdd(&h[run_bin], run);
+    digit_flush(r, h);
     if (top > 0)
       for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hn[i] = 0;
     __syncthreads();
-    if (threadIdx.x < 64) {
-      const uint32_t l = threadIdx.x;
-      const uint32_t c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
-      const uint32_t s = c0 + c1 + c2 + c3;
-      const uint32_t incl = wave_incl_scan(s);
-      const uint32_t excl = incl - s;
-      if (excl <= k && k < incl) {
-        uint32_t digit, run;
-        if (k < excl + c0) {
-          digit = 4 * l;
-          run = excl;
-        } else if (k < excl + c0 + c1) {
-          digit = 4 * l + 1;
-          run = excl + c0;
-        } else if (k < excl + c0 + c1 + c2) {
-          digit = 4 * l + 2;
-          run = excl + c0 + c1;
-        } else {
-          digit = 4 * l + 3;
-          run = excl + c0 + c1 + c2;
-        }
-        out[0] = digit;
-        out[1] = k - run;
-      }
-    }
+    if (threadIdx.x < 64) digit_pick(h, k, out);
     __syncthreads();
     const uint32_t digit = out[0];
     k = out[1];
@@ -305,6 +372,146 @@ __device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32
   }
   __syncthreads();
   return val_of(prefix + lo);
+}
+
+// ... of the values m[0..cnt) (in LDS or device memory)
+template <typename R>
+__device__ __forceinline__ R block_kth_smallest(const R *m, uint32_t cnt, uint32_t k, uint32_t *hist,
+                                                uint32_t *sh, R above = (R)-1,
+                                                typename CT<R>::K lo = 0,
+                                                typename CT<R>::K hi = ~(typename CT<R>::K)0) {
+  const R none[1] = {(R)-1};
+  return radix_select<R, 1, false>(SelSrc<R, 1, false>{none, 0u, m, cnt}, k, hist, sh, above, lo, hi);
+}
+
+// The ka-th (and with TWO also the kb-th) smallest (0-based) of the block's
+// non-negative float values held in registers: thread t holds v[j], j < per
+// (uniform), negative where it has no value.  Radix selection on key - lo as
+// in radix_select, trimmed for registers: the keys are formed once, with bit
+// 31 set for empty slots so that one mask-and-compare per pass also excludes
+// them (a real key - lo is below 2^31); the count adds one per matching key
+// (no runs); a value slot none of whose wave's keys match skips its atomic;
+// waves 0 and 1 pick the two digits.  `hist` has 3 x 512 words (histogram
+// pairs in turn), `sh` 8 words.
+template <bool TWO, int NPER>
+__device__ __forceinline__ void select_regs(const float (&v)[NPER], uint32_t per, uint32_t ka, uint32_t kb,
+                                            uint32_t *hist, uint32_t *sh, uint32_t lo, uint32_t hi, float &va,
+                                            float &vb) {
+  const int nbits = hi > lo ? bit_length(hi - lo) : 1;
+  uint32_t key[NPER];
+#pragma unroll
+  for (int j = 0; j < NPER; ++j) key[j] = (uint32_t)j < per && v[j] >= 0.f ? key_of(v[j]) - lo : 0xFFFFFFFFu;
+  for (uint32_t i = threadIdx.x; i < 1024; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  uint32_t pa = 0, pb = 0, mask = 0x80000000u;
+  int pass = 0;
+  for (int top = nbits; top > 0; ++pass) {
+    const int width = top < 8 ? top : 8;
+    const int shift = top - width;
+    top = shift;
+    const uint32_t dmask = (1u << width) - 1u;
+    uint32_t *ha = hist + 512 * (pass % 3), *hb = ha + 256;
+    uint32_t *hn = hist + 512 * ((pass + 1) % 3);
+#pragma unroll
+    for (int j = 0; j < NPER; ++j) {
+      const uint32_t kp = key[j] & mask;
+      const bool ma = kp == pa, mb = TWO && kp == pb;
+      if (__ballot(ma || mb) == 0) continue;
+      const uint32_t bin = (key[j] >> shift) & dmask;
+      if (ma)
+        atomicAdd(&ha[bin], 1u);
+      else if (mb)
+        atomicAdd(&hb[bin], 1u);
+    }
+    if (top > 0)
+      for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hn[i] = 0;
+    __syncthreads();
+    uint32_t *out = sh + 4 * (pass & 1);
+    if (threadIdx.x < 64)
+      digit_pick(ha, ka, out);
+    else if (TWO && threadIdx.x < 128)
+      digit_pick(pa == pb ? ha : hb, kb, out + 2);
+    __syncthreads();
+    pa |= out[0] << shift;
+    ka = out[1];
+    if (TWO) {
+      pb |= out[2] << shift;
+      kb = out[3];
+    }
+    mask |= dmask << shift;
+  }
+  va = val_of(pa + lo);
+  vb = val_of(pb + lo);
+}
+
+// The ka-th and kb-th smallest (0-based) of a block's non-negative values in
+// one series of digit passes: both searches share each pass's scan over the
+// values; while their prefixes agree they share its histogram, after that
+// each counts the values of its own prefix.  `hist` has 4 x 256 words (a pair
+// per pass, in turn), `sh` 8 words; digits and range as in radix_select.
+template <typename R, int NPER, bool REGS>
+__device__ __forceinline__ void radix_select2(const SelSrc<R, NPER, REGS> &src, uint32_t ka, uint32_t kb,
+                                              uint32_t *hist, uint32_t *sh, typename CT<R>::K lo,
+                                              typename CT<R>::K hi, R &va, R &vb) {
+  using K = typename CT<R>::K;
+  const int nbits = hi > lo ? bit_length(hi - lo) : 1;
+  K pa = 0, pb = 0, mask = 0;
+  for (uint32_t i = threadIdx.x; i < 1024; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  int pass = 0;
+  for (int top = nbits; top > 0; ++pass) {
+    const int width = top < 8 ? top : 8;
+    const int shift = top - width;
+    top = shift;
+    const uint32_t dmask = (1u << width) - 1u;
+    uint32_t *ha = hist + 512 * (pass & 1), *hb = ha + 256;
+    uint32_t *hn = hist + 512 * ((pass + 1) & 1);
+    uint32_t *out = sh + 4 * (pass & 1);
+    const bool apart = pa != pb;  // otherwise every value counts in ha
+    DigitRun ra = {0, 0}, rb = {0, 0};
+    if constexpr (REGS) {
+#pragma unroll
+      for (int j = 0; j < NPER; ++j) {
+        if ((uint32_t)j < src.per) {
+          const R mb = src.v[j];
+          const K key = key_of(mb) - lo, kp = key & mask;
+          const uint32_t bin = (uint32_t)(key >> shift) & dmask;
+          const bool ok = mb >= (R)0;
+          digit_add(ra, ha, bin, ok && kp == pa);
+          digit_add(rb, hb, bin, ok && kp == pb && kp != pa);
+        }
+      }
+    } else {
+      for (uint32_t b = threadIdx.x; b < src.cnt; b += blockDim.x) {
+        const R mb = src.m[b];
+        const K key = key_of(mb) - lo, kp = key & mask;
+        const uint32_t bin = (uint32_t)(key >> shift) & dmask;
+        const bool ok = mb >= (R)0;
+        digit_add(ra, ha, bin, ok && kp == pa);
+        digit_add(rb, hb, bin, ok && kp == pb && kp != pa);
+      }
+    }
+    digit_flush(ra, ha);
+    digit_flush(rb, hb);
+    if (top > 0)
+      for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hn[i] = 0;
+    __syncthreads();
+    // wave 0 searches for ka, wave 1 for kb (in the shared histogram while
+    // the prefixes agree)
+    if (threadIdx.x < 64)
+      digit_pick(ha, ka, out);
+    else if (threadIdx.x < 128)
+      digit_pick(apart ? hb : ha, kb, out + 2);
+    __syncthreads();
+    pa |= (K)out[0] << shift;
+    ka = out[1];
+    pb |= (K)out[2] << shift;
+    kb = out[3];
+    mask |= (K)dmask << shift;
+  }
+  __syncthreads();
+  va = val_of(pa + lo);
+  vb = val_of(pb + lo);
 }
 
 // ------------------------------------------------------------- k_init ----
@@ -1160,6 +1367,11 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   const uint32_t Bc = NDIM == 1 ? B : B * B;
   if (Bc > P.lds_cap) return;  // a large array: k_big_rows, k_big_cols, k_big_stats
   const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
+  // what the statistics read from device memory, read before the bucket
+  // stores below: a vector load after them would wait for every one of them
+  const int32_t khat_in = st->khat;
+  const double q_in = P.q, noise_rate_in = P.noise_rate, neg_log1mq_in = P.neg_log1mq, rho_in = P.rho;
+  const uint32_t d_in = P.d;
   const uint32_t tid = threadIdx.x, T = blockDim.x;
 
   // bucket DFT
@@ -1234,7 +1446,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
 #pragma unroll
   for (int j = 0; j < kBucketMaxPer; ++j) {
     const uint32_t b = tid + (uint32_t)j * T;
-    mv[j] = 0;
+    mv[j] = (R)-1;  // no bucket: below every threshold and select
     if ((uint32_t)j < per && b < Bc) {
       const C v = buf[lds_at<true>(b)];
       yg[b] = v;
@@ -1244,23 +1456,25 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
     }
   }
   if (!stats) return;
-  for (int o = 32; o > 0; o >>= 1) {
-    const K other = __shfl_xor(kmax, o), other_min = __shfl_xor(kmin, o);
-    kmax = max(kmax, other);
-    kmin = min(kmin, other_min);
-  }
+  kmax = wave_extreme<true>(kmax);
+  kmin = wave_extreme<false>(kmin);
   R *ms = reinterpret_cast<R *>(smem);
-  // LDS after the DFT: m, room for the keys above T, then the select's scratch
-  R *above_keys = reinterpret_cast<R *>(smem + (((size_t)Bc * sizeof(R) + 15) & ~(size_t)15));
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)2 * Bc * sizeof(R) + 15) & ~(size_t)15));
-  uint32_t *sh = hist + 512;               // 32 words of scratch
+  // LDS after the DFT: m (probe levels; c128 also for the selects), then the
+  // selects' histograms and scratch
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + (((size_t)Bc * sizeof(R) + 15) & ~(size_t)15));
+  uint32_t *sh = hist + 1536;              // 32 words of scratch
   K *wmax = reinterpret_cast<K *>(sh + 32);  // one key per wave
   K *wmin = wmax + kBucketThreads / 64;
   __syncthreads();
+  // m in LDS for the probe's neighbour tests, and in c128 for the selects
+  // (c64 selects read the registers; c128's sixteen values would not fit)
+  constexpr bool kRegSel = sizeof(R) == 4;
+  if (!main_phase || !kRegSel) {
 #pragma unroll
-  for (int j = 0; j < kBucketMaxPer; ++j) {
-    const uint32_t b = tid + (uint32_t)j * T;
-    if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      const uint32_t b = tid + (uint32_t)j * T;
+      if ((uint32_t)j < per && b < Bc) ms[b] = mv[j];
+    }
   }
   if ((tid & 63) == 0) {
     wmax[tid >> 6] = kmax;
@@ -1270,16 +1484,36 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
 
   // threshold: noise floor from the floor(q (Bc-1))-th order statistic,
   // c_noise = ln(Bc / noise_rate), and the relative floor rho * max m
-  for (uint32_t wv = 0; wv < (T + 63) / 64; ++wv) {
-    kmax = max(kmax, wmax[wv]);
-    kmin = min(kmin, wmin[wv]);
+  {
+    const uint32_t ln = tid & 63u, nw = (T + 63) / 64;
+    kmax = wave_extreme<true>(ln < nw ? wmax[ln] : (K)0);
+    kmin = wave_extreme<false>(ln < nw ? wmin[ln] : ~(K)0);
   }
   const R mmax = val_of(kmax);
-  const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
-  const R floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh, (R)-1, kmin, kmax);
-  const double c_noise = log((double)Bc / P.noise_rate);
-  const double t1 = c_noise * ((double)floor_m / P.neg_log1mq);
-  const double t2 = P.rho * (double)mmax;
+  const uint32_t qi = (uint32_t)floor(q_in * (double)(Bc - 1));
+  // location loops: the cutoff value v (the num-th largest above T, when
+  // more than num values exceed T) is the overall order statistic of rank
+  // Bc - num, so it is selected in the same passes as the noise floor
+  uint32_t num = 0;
+  R floor_m, vcut = 0;
+  if (main_phase) {
+    num = d_in * (uint32_t)max(khat_in, 0);
+    if (num > Bc) num = Bc;
+    const uint32_t kb = num > 0 ? Bc - num : 0u;
+    if constexpr (kRegSel)
+      select_regs<true>(mv, per, qi, kb, hist, sh + 24, kmin, kmax, floor_m, vcut);
+    else
+      radix_select2<R, kBucketMaxPer, false>(SelSrc<R, kBucketMaxPer, false>{mv, 0u, ms, Bc}, qi, kb, hist, sh + 24,
+                                             kmin, kmax, floor_m, vcut);
+  } else if constexpr (kRegSel) {
+    R unused;
+    select_regs<false>(mv, per, qi, 0u, hist, sh + 24, kmin, kmax, floor_m, unused);
+  } else {
+    floor_m = block_kth_smallest<R>(ms, Bc, qi, hist, sh, (R)-1, kmin, kmax);
+  }
+  const double c_noise = log((double)Bc / noise_rate_in);
+  const double t1 = c_noise * ((double)floor_m / neg_log1mq_in);
+  const double t2 = rho_in * (double)mmax;
   const double Td = t1 > t2 ? t1 : t2;
   const R Tr = (R)Td;
 
@@ -1381,36 +1615,19 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   // index order (v = T and need = 0 when all above T fit).  A thread's keys
   // are still in mv; the list is built in index order from 64-bucket chunks,
   // one wave ballot each, so no LDS pass runs over a thread's own chunk.
-  uint32_t above = 0;
+  // #{m > T} and #{m > vcut} in one block sum (each at most 16384)
+  uint32_t cnt2 = 0;
 #pragma unroll
   for (int j = 0; j < kBucketMaxPer; ++j) {
-    const uint32_t b = tid + (uint32_t)j * T;
-    above += (uint32_t)j < per && b < Bc && mv[j] > Tr ? 1u : 0u;
+    if ((uint32_t)j < per) cnt2 += (mv[j] > Tr ? 65536u : 0u) + (mv[j] > vcut ? 1u : 0u);
   }
-  if (tid == 0) sh[7] = 0;  // the count of keys above T gathered below
-  const uint32_t n_above = block_sum(above, &sh[4]);
-  uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
-  if (num > Bc) num = Bc;
+  cnt2 = block_sum(cnt2, &sh[4]);
+  const uint32_t n_above = cnt2 >> 16;
   R v = Tr;
   uint32_t need = 0;
   if (n_above > num) {
-    // the num-th largest: among the n_above values above T, the
-    // (n_above - num)-th smallest, selected from those values gathered into
-    // their own LDS array (in any order) so that the radix passes scan only them
-#pragma unroll
-    for (int j = 0; j < kBucketMaxPer; ++j) {
-      const uint32_t b = tid + (uint32_t)j * T;
-      if ((uint32_t)j < per && b < Bc && mv[j] > Tr) above_keys[atomicAdd(&sh[7], 1u)] = mv[j];
-    }
-    __syncthreads();
-    v = block_kth_smallest<R>(above_keys, n_above, n_above - num, hist, sh);
-    uint32_t gt = 0;
-#pragma unroll
-    for (int j = 0; j < kBucketMaxPer; ++j) {
-      const uint32_t b = tid + (uint32_t)j * T;
-      gt += (uint32_t)j < per && b < Bc && mv[j] > v ? 1u : 0u;
-    }
-    need = num - block_sum(gt, &sh[4]);
+    v = vcut;
+    need = num - (cnt2 & 0xFFFFu);
   }
   // per chunk (Bc / 64 <= 256 of them): buckets above v, buckets equal to v
   const uint32_t lane = tid & 63u;
@@ -1610,6 +1827,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
   const BigArr<C> ar = big_arr<C>(P, sig, role, idx);
   if (!ar.ok) return;
   SigState *st = state_of(P, sig);
+  const int32_t khat_in = st->khat;  // read before the m stores below
   const uint32_t B = ar.B, logB = ilog2(B);
   const uint32_t Bc = B * B, nch = Bc >> 6;
   uint32_t *ce = cg + nch;
@@ -1624,19 +1842,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
     kmax = max(kmax, key_of(mb));
     kmin = min(kmin, key_of(mb));
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    kmax = max(kmax, (K)__shfl_xor(kmax, o));
-    kmin = min(kmin, (K)__shfl_xor(kmin, o));
-  }
+  kmax = wave_extreme<true>(kmax);
+  kmin = wave_extreme<false>(kmin);
   if (lane == 0) {
     wk[2 * wave] = kmax;
     wk[2 * wave + 1] = kmin;
   }
   __syncthreads();
-  for (uint32_t w = 0; w < nw; ++w) {
-    kmax = max(kmax, wk[2 * w]);
-    kmin = min(kmin, wk[2 * w + 1]);
-  }
+  kmax = wave_extreme<true>(lane < nw ? wk[2 * lane] : (K)0);
+  kmin = wave_extreme<false>(lane < nw ? wk[2 * lane + 1] : ~(K)0);
   // threshold: as k_bucket (noise floor from the floor(q (Bc-1))-th order
   // statistic, c_noise = ln(Bc / noise_rate), relative floor rho * max m)
   const R mmax = val_of(kmax);
@@ -1682,7 +1896,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
   uint32_t above = 0;
   for (uint32_t b = tid; b < Bc; b += T) above += m[b] > Tr ? 1u : 0u;
   const uint32_t n_above = block_sum(above, &sh[4]);
-  uint32_t num = (uint32_t)P.d * (uint32_t)max(st->khat, 0);
+  uint32_t num = (uint32_t)P.d * (uint32_t)max(khat_in, 0);
   if (num > Bc) num = Bc;
   R v = Tr;
   uint32_t need = 0;
@@ -1715,8 +1929,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
     te += ce[c];
     ss += sel;
   }
-  uint32_t pos = block_excl_scan(ss, sh);
-  const uint32_t total = block_sum(ss, &sh[4]);
+  uint32_t total;
+  uint32_t pos = block_excl_scan(ss, sh, &total);
   te -= es;  // back to the ties before this thread's first chunk
   for (uint32_t c = c_lo; c < c_hi; ++c) {
     const uint32_t sel = cg[c] + min(ce[c], need > te ? need - te : 0u);
@@ -2629,7 +2843,7 @@ hipError_t scratch_address(int device, void **ptr) {
 size_t bucket_smem_bytes(int dtype, uint32_t Bc_max) {
   const size_t rs = dtype == 0 ? sizeof(float) : sizeof(double);
   const size_t fft = 2 * rs * (Bc_max + Bc_max / 32);  // one pad element per 32
-  const size_t sel = ((2 * rs * Bc_max + 15) & ~(size_t)15) + 4 * (512 + 32) + 2 * 8 * (kBucketThreads / 64);
+  const size_t sel = ((rs * Bc_max + 15) & ~(size_t)15) + 4 * (1536 + 32) + 2 * 8 * (kBucketThreads / 64);
   return fft > sel ? fft : sel;
 }
 
