@@ -208,6 +208,10 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  *                        with ATSFFT_SIG_PROBE_TIMEOUT, 0..2^24 (2^20)
  *   ATSFFT_PROBE_DROP_LEVEL  test hook: the probe level whose count is never
  *                        recorded, so that the wait gives up (unset: none)
+ *   ATSFFT_CUTOFF_TIES   test hook, 1: the location loops' top-num cutoff
+ *                        always takes its path for buckets tied at the cut
+ *                        (taken in index order), which otherwise runs only
+ *                        when more buckets equal the cut value than it takes
  */
 atsfft_status atsfft_plan(atsfft_plan_t *out, const atsfft_desc *d);
 

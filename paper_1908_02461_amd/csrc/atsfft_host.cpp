@@ -24,6 +24,7 @@ struct atsfft_plan_s {
   uint32_t Bc_max;   // largest bucket array (B^ndim) any loop can use
   uint32_t big;      // 2D arrays above the LDS-resident size: DFTs and cutoffs in device memory
   uint32_t lds_cap;  // largest bucket array (B^ndim) k_bucket holds in LDS
+  uint32_t n_cu;     // compute units of the device
   void *G_dev;       // taps, plan precision
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t tab_host[128];  // element offsets by log2 B (passed in the kernel arguments)
@@ -40,6 +41,7 @@ struct atsfft_plan_s {
   uint32_t probe_slabs; // 1D probe levels: address slabs
   uint32_t probe_spin;  // sleeps before the probe control gives up waiting for a count
   int32_t probe_drop;   // test hook: probe level whose count is never recorded (-1: none)
+  uint32_t cut_ties;    // test hook: the location loops' tie-aware cutoff path always
   // stage timing (ATSFFT_FLAG_PROFILE): six events per execute
   std::vector<std::array<hipEvent_t, 6>> prof_used, prof_free;
   // uneven batches: one plan per power-of-two length below n (index log2 n'),
@@ -307,6 +309,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.probe_slabs = plan->probe_slabs;
   P.probe_spin = plan->probe_spin;
   P.probe_drop = plan->probe_drop;
+  P.cut_ties = plan->cut_ties;
+  P.pad_kp = 0;
   P.tile_slots = plan->tile_slots;
   P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
@@ -319,6 +323,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.comp = (d.flags & ATSFFT_FLAG_COMPENSATED) && d.dtype == ATSFFT_C64 ? 1u : 0u;
   P.big = plan->big;
   P.lds_cap = plan->lds_cap;
+  P.n_cu = plan->n_cu;
+  P.est_wait = 0;
   P.q = d.q;
   P.neg_log1mq = -std::log(1.0 - d.q);
   P.noise_rate = d.noise_rate;
@@ -545,9 +551,12 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 0 && v < kMaxProbe) p->probe_drop = (int32_t)v;
   }
+  p->cut_ties = 0;
+  if (const char *env = std::getenv("ATSFFT_CUTOFF_TIES")) p->cut_ties = std::strtol(env, nullptr, 10) == 1 ? 1u : 0u;
   p->est_smem = estimate_smem_bytes((uint32_t)d->max_out);
   p->big = 0;
   p->lds_cap = p->Bc_max;
+  p->n_cu = (uint32_t)prop.multiProcessorCount;
   if (p->bucket_smem > prop.sharedMemPerBlock) {
     // 2D arrays above the LDS size (the known-k form at the sparse FFT's
     // bucket count, or a B_max beyond it): those arrays live in device

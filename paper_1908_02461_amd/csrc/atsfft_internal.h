@@ -55,7 +55,8 @@ struct SigState {
   int32_t pass;     // location/estimation pass of the residual test (draw iterations + 32 pass)
   double res_ratio; // E_res / E_tot of the last pass (residual test)
   uint32_t round_blocks;  // probe workgroups of the current round that have recorded their count
-  int32_t pad[3];
+  uint32_t loc_loaded;    // location-loop k_bucket workgroups that have read their partials (all passes)
+  int32_t pad[2];
 };
 static_assert(sizeof(SigState) == 64, "SigState layout");
 
@@ -105,6 +106,11 @@ struct KParams {
   uint32_t comp;         // FP32 fold sums compensated (Neumaier), slab partials added in FP64
   uint32_t big;          // 2D bucket arrays above the LDS-resident size: DFTs and cutoffs in device memory
   uint32_t lds_cap;      // largest bucket array (B^ndim) k_bucket holds in LDS
+  uint32_t n_cu;         // compute units of the device
+  uint32_t est_wait;     // main k_bucket: estimation loops read their partials after the signal's
+                         // location loops have (set for launches whose whole grid is resident)
+  uint32_t cut_ties;     // test hook: location loops always take the tie-aware cutoff path
+  uint32_t pad_kp;
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
   int64_t tab[128];    // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),

@@ -534,6 +534,7 @@ __global__ void k_init(KParams P0, int batch) {
   s.pass = 0;
   s.res_ratio = 0.0;
   s.round_blocks = 0;
+  s.loc_loaded = 0;
   for (int i = 0; i < 3; ++i) s.pad[i] = 0;
   if (P.fixed) {
     s.done = 1;
@@ -1372,6 +1373,23 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   const int32_t khat_in = st->khat;
   const double q_in = P.q, noise_rate_in = P.noise_rate, neg_log1mq_in = P.neg_log1mq, rho_in = P.rho;
   const uint32_t d_in = P.d;
+  const bool cut_ties_in = P.cut_ties != 0u;
+  // With the whole grid resident, an estimation loop leaves the memory system
+  // to its signal's location loops until they have read their partials: the
+  // location loops go on to the threshold and cutoff, the longer chain.  The
+  // location loops have lower workgroup indices, so they were dispatched
+  // first; the wait is bounded all the same.
+  const bool est_wait = main_phase && P.est_wait;
+  if (est_wait && loop >= P.L_loc) {
+    if (threadIdx.x == 0) {
+      const uint32_t target = P.L_loc * (uint32_t)(st->pass + 1);
+      for (uint32_t spin = 0; spin < 4096u; ++spin) {
+        if (__hip_atomic_load(&st->loc_loaded, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+        __builtin_amdgcn_s_sleep(8);
+      }
+    }
+    __syncthreads();
+  }
   const uint32_t tid = threadIdx.x, T = blockDim.x;
 
   // bucket DFT
@@ -1382,49 +1400,100 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   };
   // the partials are added in slab (or row-wrap) order: the streamed 2D row
   // hash leaves one per row wrap, the row hash one in all, k_hash kSlabs; the
-  // compensated FP32 fold adds them in FP64.  kSumU buckets per thread have
-  // their loads issued together.
+  // compensated FP32 fold adds them in FP64.  A thread's buckets have their
+  // loads issued together.
   const uint32_t nsl = !main_phase ? (NDIM == 1 ? P.probe_slabs : 1u)
                        : P.rows2d == 1 ? 1u
                        : P.rows2d == 2 ? (min(P.alpha * B, P.n) >> logB)
                                        : (uint32_t)kSlabs;
-  constexpr int kSumU = sizeof(R) == 4 ? 4 : 2;
-  for (uint32_t b0 = tid; b0 < Bc; b0 += kSumU * T) {
-    C u[kSumU][kSlabs];
+  if constexpr (sizeof(R) == 4) {
+    // c64: two neighbouring buckets per 16-byte load (bucket counts and slab
+    // strides are even), two pairs per thread in flight; the same order of
+    // addition
+    const bool comp = P.comp && !(main_phase && P.rows2d);
+    for (uint32_t p0 = tid; 2u * p0 < Bc; p0 += 2u * T) {
+      float4 u[2][kSlabs];
 #pragma unroll
-    for (int k = 0; k < kSumU; ++k) {
-      const uint32_t b = b0 + (uint32_t)k * T;
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t p = p0 + (uint32_t)k * T;
 #pragma unroll
-      for (int sl = 0; sl < kSlabs; ++sl) {
-        u[k][sl].x = 0;
-        u[k][sl].y = 0;
-        if (b < Bc && (uint32_t)sl < nsl) u[k][sl] = yg[(size_t)sl * sstride + b];
+        for (int sl = 0; sl < kSlabs; ++sl) {
+          u[k][sl] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (2u * p < Bc && (uint32_t)sl < nsl)
+            u[k][sl] = *reinterpret_cast<const float4 *>(yg + (size_t)sl * sstride + 2u * p);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t p = p0 + (uint32_t)k * T;
+        float4 v = u[k][0];
+        if (comp) {
+          double a = v.x, b = v.y, c = v.z, d = v.w;
+#pragma unroll
+          for (int sl = 1; sl < kSlabs; ++sl) {
+            a += (double)u[k][sl].x;
+            b += (double)u[k][sl].y;
+            c += (double)u[k][sl].z;
+            d += (double)u[k][sl].w;
+          }
+          v = make_float4((float)a, (float)b, (float)c, (float)d);
+        } else {
+#pragma unroll
+          for (int sl = 1; sl < kSlabs; ++sl) {
+            const bool on = (uint32_t)sl < nsl;
+            v.x += on ? u[k][sl].x : 0.f;
+            v.y += on ? u[k][sl].y : 0.f;
+            v.z += on ? u[k][sl].z : 0.f;
+            v.w += on ? u[k][sl].w : 0.f;
+          }
+        }
+        if (2u * p < Bc) {
+          buf[lds_at<true>(dst_of(2u * p))] = make_float2(v.x, v.y);
+          buf[lds_at<true>(dst_of(2u * p + 1u))] = make_float2(v.z, v.w);
+        }
       }
     }
+  } else {
+    constexpr int kSumU = sizeof(R) == 4 ? 4 : 2;
+    for (uint32_t b0 = tid; b0 < Bc; b0 += kSumU * T) {
+      C u[kSumU][kSlabs];
 #pragma unroll
-    for (int k = 0; k < kSumU; ++k) {
-      const uint32_t b = b0 + (uint32_t)k * T;
-      C v = u[k][0];
-      if (P.comp && !(main_phase && P.rows2d)) {
-        double vx = v.x, vy = v.y;
+      for (int k = 0; k < kSumU; ++k) {
+        const uint32_t b = b0 + (uint32_t)k * T;
 #pragma unroll
-        for (int sl = 1; sl < kSlabs; ++sl) {
-          vx += (double)u[k][sl].x;
-          vy += (double)u[k][sl].y;
-        }
-        v.x = (R)vx;
-        v.y = (R)vy;
-      } else {
-#pragma unroll
-        for (int sl = 1; sl < kSlabs; ++sl) {
-          v.x += (uint32_t)sl < nsl ? u[k][sl].x : (R)0;
-          v.y += (uint32_t)sl < nsl ? u[k][sl].y : (R)0;
+        for (int sl = 0; sl < kSlabs; ++sl) {
+          u[k][sl].x = 0;
+          u[k][sl].y = 0;
+          if (b < Bc && (uint32_t)sl < nsl) u[k][sl] = yg[(size_t)sl * sstride + b];
         }
       }
-      if (b < Bc) buf[lds_at<true>(dst_of(b))] = v;
+#pragma unroll
+      for (int k = 0; k < kSumU; ++k) {
+        const uint32_t b = b0 + (uint32_t)k * T;
+        C v = u[k][0];
+        if (P.comp && !(main_phase && P.rows2d)) {
+          double vx = v.x, vy = v.y;
+#pragma unroll
+          for (int sl = 1; sl < kSlabs; ++sl) {
+            vx += (double)u[k][sl].x;
+            vy += (double)u[k][sl].y;
+          }
+          v.x = (R)vx;
+          v.y = (R)vy;
+        } else {
+#pragma unroll
+          for (int sl = 1; sl < kSlabs; ++sl) {
+            v.x += (uint32_t)sl < nsl ? u[k][sl].x : (R)0;
+            v.y += (uint32_t)sl < nsl ? u[k][sl].y : (R)0;
+          }
+        }
+        if (b < Bc) buf[lds_at<true>(dst_of(b))] = v;
+      }
     }
   }
   __syncthreads();
+  if (est_wait && loop < P.L_loc && threadIdx.x == 0)
+    __hip_atomic_fetch_add(&st->loc_loaded, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (NDIM == 1) {
     // radix-16 passes once a pass has groups for half the workgroup
     if (logB >= 13)
@@ -1615,88 +1684,144 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   // index order (v = T and need = 0 when all above T fit).  A thread's keys
   // are still in mv; the list is built in index order from 64-bucket chunks,
   // one wave ballot each, so no LDS pass runs over a thread's own chunk.
-  // #{m > T} and #{m > vcut} in one block sum (each at most 16384)
+  // #{m > T} and #{m >= vcut} in one block sum (each at most 16384)
   uint32_t cnt2 = 0;
 #pragma unroll
   for (int j = 0; j < kBucketMaxPer; ++j) {
-    if ((uint32_t)j < per) cnt2 += (mv[j] > Tr ? 65536u : 0u) + (mv[j] > vcut ? 1u : 0u);
+    if ((uint32_t)j < per) cnt2 += (mv[j] > Tr ? 65536u : 0u) + (mv[j] >= vcut ? 1u : 0u);
   }
   cnt2 = block_sum(cnt2, &sh[4]);
-  const uint32_t n_above = cnt2 >> 16;
-  R v = Tr;
-  uint32_t need = 0;
-  if (n_above > num) {
-    v = vcut;
-    need = num - (cnt2 & 0xFFFFu);
-  }
-  // per chunk (Bc / 64 <= 256 of them): buckets above v, buckets equal to v
+  const uint32_t n_above = cnt2 >> 16, n_ge = cnt2 & 0xFFFFu;
   const uint32_t lane = tid & 63u;
   uint32_t *cg = hist, *ce = hist + 256;
-#pragma unroll
-  for (int j = 0; j < kBucketMaxPer; ++j) {
-    if ((uint32_t)j < per) {  // uniform over the block
-      const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
-      const unsigned long long g = __ballot(b < Bc && mv[j] > v);
-      const unsigned long long e = __ballot(b < Bc && need > 0u && mv[j] == v);
-      if (lane == 0 && b0 < Bc) {
-        cg[b0 >> 6] = (uint32_t)__popcll(g);
-        ce[b0 >> 6] = (uint32_t)__popcll(e);
-      }
-    }
-  }
-  __syncthreads();
-  if (tid < 64) {
-    // one wave scans the chunks, four per lane: ties before each chunk, then
-    // list positions (the chunk's taken ties are the first `need` overall)
-    const uint32_t nch = (Bc + 63u) >> 6;
-    uint32_t g4[4], e4[4], te[4], sel[4], es = 0, ss = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t c = 4u * tid + (uint32_t)i;
-      g4[i] = c < nch ? cg[c] : 0u;
-      e4[i] = c < nch ? ce[c] : 0u;
-      es += e4[i];
-    }
-    uint32_t run = wave_incl_scan(es) - es;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      te[i] = run;
-      run += e4[i];
-      sel[i] = g4[i] + min(e4[i], need > te[i] ? need - te[i] : 0u);
-      ss += sel[i];
-    }
-    const uint32_t incl = wave_incl_scan(ss);
-    run = incl - ss;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t c = 4u * tid + (uint32_t)i;
-      if (c < nch) {
-        cg[c] = run;
-        ce[c] = te[i];
-      }
-      run += sel[i];
-    }
-    if (tid == 63) sh[6] = incl;
-  }
-  __syncthreads();
-  const uint32_t total = sh[6];
-  // the list in index order and the cutoff bitmap, one ballot per chunk
   int32_t *jl = jlist_of(P, sig, loop);
   uint32_t *jb = jbits_of(P, sig, loop);
+  // J is {m > T} when every bucket above T fits, else {m >= vcut} when no
+  // more buckets equal vcut than the cutoff takes (the usual case: one);
+  // otherwise the buckets above vcut and, of those equal to it, the first
+  // `need` in index order
+  const bool fits = n_above <= num;
+  const R v = fits ? Tr : vcut;
+  uint32_t total;
+  if ((fits || n_ge == num) && !cut_ties_in) {
+    // per chunk (a wave's 64 buckets of one j; Bc / 64 <= 256 of them): the
+    // taken buckets' count and bitmap words, then one wave scans the counts
 #pragma unroll
-  for (int j = 0; j < kBucketMaxPer; ++j) {
-    if ((uint32_t)j < per) {  // uniform over the block
-      const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
-      const bool ok = b < Bc;
-      const bool eq = ok && need > 0u && mv[j] == v;
-      const unsigned long long e = __ballot(eq);
-      const uint32_t c = b0 >> 6;
-      const bool f = (ok && mv[j] > v) || (eq && ce[c] + lanes_below(e) < need);
-      const unsigned long long fm = __ballot(f);
-      if (f) jl[cg[c] + lanes_below(fm)] = (int32_t)b;
-      if (lane == 0 && b0 < Bc) {
-        jb[b0 >> 5] = (uint32_t)fm;
-        if (b0 + 32u < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(fm >> 32);
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      if ((uint32_t)j < per) {  // uniform over the block
+        const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T;
+        const unsigned long long fm = __ballot(fits ? mv[j] > v : mv[j] >= v);
+        if (lane == 0 && b0 < Bc) {
+          cg[b0 >> 6] = (uint32_t)__popcll(fm);
+          jb[b0 >> 5] = (uint32_t)fm;
+          if (b0 + 32u < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(fm >> 32);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const uint32_t nch = (Bc + 63u) >> 6;
+      uint32_t g4[4], ss = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t c = 4u * tid + (uint32_t)i;
+        g4[i] = c < nch ? cg[c] : 0u;
+        ss += g4[i];
+      }
+      const uint32_t incl = wave_incl_scan(ss);
+      uint32_t run = incl - ss;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t c = 4u * tid + (uint32_t)i;
+        if (c < nch) cg[c] = run;
+        run += g4[i];
+      }
+      if (tid == 63) sh[6] = incl;
+    }
+    __syncthreads();
+    total = sh[6];
+    // the list in index order
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      if ((uint32_t)j < per) {
+        const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T;
+        const bool f = fits ? mv[j] > v : mv[j] >= v;
+        const unsigned long long fm = __ballot(f);
+        if (f) jl[cg[b0 >> 6] + lanes_below(fm)] = (int32_t)(b0 + lane);
+      }
+    }
+  } else {
+    uint32_t gt = 0;
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      if ((uint32_t)j < per) gt += mv[j] > vcut ? 1u : 0u;
+    }
+    const uint32_t need = num - block_sum(gt, &sh[4]);
+    // per chunk (Bc / 64 <= 256 of them): buckets above v, buckets equal to v
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      if ((uint32_t)j < per) {  // uniform over the block
+        const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
+        const unsigned long long g = __ballot(b < Bc && mv[j] > v);
+        const unsigned long long e = __ballot(b < Bc && need > 0u && mv[j] == v);
+        if (lane == 0 && b0 < Bc) {
+          cg[b0 >> 6] = (uint32_t)__popcll(g);
+          ce[b0 >> 6] = (uint32_t)__popcll(e);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // one wave scans the chunks, four per lane: ties before each chunk, then
+      // list positions (the chunk's taken ties are the first `need` overall)
+      const uint32_t nch = (Bc + 63u) >> 6;
+      uint32_t g4[4], e4[4], te[4], sel[4], es = 0, ss = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t c = 4u * tid + (uint32_t)i;
+        g4[i] = c < nch ? cg[c] : 0u;
+        e4[i] = c < nch ? ce[c] : 0u;
+        es += e4[i];
+      }
+      uint32_t run = wave_incl_scan(es) - es;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        te[i] = run;
+        run += e4[i];
+        sel[i] = g4[i] + min(e4[i], need > te[i] ? need - te[i] : 0u);
+        ss += sel[i];
+      }
+      const uint32_t incl = wave_incl_scan(ss);
+      run = incl - ss;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t c = 4u * tid + (uint32_t)i;
+        if (c < nch) {
+          cg[c] = run;
+          ce[c] = te[i];
+        }
+        run += sel[i];
+      }
+      if (tid == 63) sh[6] = incl;
+    }
+    __syncthreads();
+    total = sh[6];
+    // the list in index order and the cutoff bitmap, one ballot per chunk
+#pragma unroll
+    for (int j = 0; j < kBucketMaxPer; ++j) {
+      if ((uint32_t)j < per) {  // uniform over the block
+        const uint32_t b0 = (tid & ~63u) + (uint32_t)j * T, b = b0 + lane;
+        const bool ok = b < Bc;
+        const bool eq = ok && need > 0u && mv[j] == v;
+        const unsigned long long e = __ballot(eq);
+        const uint32_t c = b0 >> 6;
+        const bool f = (ok && mv[j] > v) || (eq && ce[c] + lanes_below(e) < need);
+        const unsigned long long fm = __ballot(f);
+        if (f) jl[cg[c] + lanes_below(fm)] = (int32_t)b;
+        if (lane == 0 && b0 < Bc) {
+          jb[b0 >> 5] = (uint32_t)fm;
+          if (b0 + 32u < Bc) jb[(b0 >> 5) + 1] = (uint32_t)(fm >> 32);
+        }
       }
     }
   }
@@ -3015,6 +3140,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
   auto main_pass = [&](const KParams &Q0, bool marks) {
     KParams Q = Q0;
+    Q.est_wait = !DEV && (uint64_t)loops * (uint64_t)batch <= (uint64_t)P.n_cu ? 1u : 0u;
     if (NDIM == 2 && Q.big) {
       // arrays above the LDS size (this branch) and the others (the usual
       // launches below) each skip the other kind, so a batch may hold both:

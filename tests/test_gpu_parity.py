@@ -261,3 +261,31 @@ def test_probe_without_occupancy_guard(A, ndim, n, k, dt, snr):
     mag = None if snr is None else ("uniform", 0.5, 1.0)
     xs = [make(n, k, s, mag=mag, snr_db=snr, dtype=npdt)[0] for s in range(3)]
     _check_batch(A, plan, xs, f"gamma=0 {ndim}D {dt}")
+
+
+@pytest.mark.parametrize("ndim,n,k,dt,snr,batch", [(1, 1 << 16, 16, "c64", 30.0, 2), (2, 1024, 40, "c64", 30.0, 2),
+                                                   (1, 1 << 14, 8, "c128", None, 1)])
+def test_cutoff_tie_path(A, monkeypatch, ndim, n, k, dt, snr, batch):
+    """The top-num cutoff has two paths: the plain one (J = {m > T}, or
+    {m >= v} when exactly num buckets reach the cut value v, the usual case)
+    and the tie-aware one (of the buckets equal to v, the first `need` in
+    index order), which inputs rarely reach since it needs bitwise-equal
+    bucket magnitudes at the cut.  A test hook forces the tie-aware path:
+    both give the same bits (cutoff bitmaps and lists, located set, values),
+    and both match the oracle."""
+    npdt = np.complex64 if dt == "c64" else np.complex128
+    mag = ("uniform", 0.5, 1.0) if snr is not None else None
+    gen = synth.planted_1d if ndim == 1 else synth.planted_2d
+    xs = [gen(n, k, 600 + i, mag=mag, snr_db=snr, dtype=npdt)[0] for i in range(batch)]
+    plain = A.Plan(ndim, n, dt, seed=17, max_batch=batch)
+    monkeypatch.setenv("ATSFFT_CUTOFF_TIES", "1")
+    ties = A.Plan(ndim, n, dt, seed=17, max_batch=batch)
+    monkeypatch.delenv("ATSFFT_CUTOFF_TIES")
+    print(f"cutoff paths: ndim={ndim} n={n} k={k} {dt}", flush=True)
+    a, _ = _check_batch(A, plain, xs, "plain cutoff")
+    b, _ = _check_batch(A, ties, xs, "tie-aware cutoff")
+    for i in range(batch):
+        u, w = plain.results(a, i), ties.results(b, i)
+        assert np.array_equal(u["locs"], w["locs"]) and np.array_equal(u["vals"], w["vals"]), i
+        tu, tw = plain.trace(a["ws"], i), ties.trace(b["ws"], i)
+        assert np.array_equal(tu["J"], tw["J"]), i
