@@ -1348,9 +1348,17 @@ template <typename R, int NDIM, bool DEV = false>
 __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_phase, int iter) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t sig = blockIdx.y;
+  uint32_t sig = blockIdx.y, loop = blockIdx.x;
+  if (main_phase == 2) {
+    // one linear grid, every signal's location loops first: their chain is
+    // the longer, and when the grid takes several rounds of the chip the
+    // short estimation loops then fill the last one
+    const uint32_t batch = gridDim.x / (P0.L_loc + P0.L_est), nloc = P0.L_loc * batch;
+    const uint32_t i = blockIdx.x;
+    loop = i < nloc ? i / batch : P0.L_loc + (i - nloc) / batch;
+    sig = (i < nloc ? i : i - nloc) % batch;
+  }
   const KParams &P = params_of<DEV>(P0, sig);
-  const uint32_t loop = blockIdx.x;
   const uint32_t level = (uint32_t)iter + blockIdx.x;
   SigState *st = state_of(P, sig);
   uint32_t B;
@@ -3163,7 +3171,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bb / big_cols<R>()), loops, batch), dim3(256),
                          big_cols_smem(dt, Bb), s, Q, 0, 0);
       hipLaunchKernelGGL((k_big_stats<R>), dim3(P.L_loc, batch), dim3(kBucketThreads), big_stats_smem(Bb), s, Q, 0, 0);
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
       if (marks && mark) mark(ctx, 3);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, Q);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads),
@@ -3193,7 +3201,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       else
         hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
       if (marks && mark) mark(ctx, 2);
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops, batch), dim3(kBucketThreads), bsmem, s, Q, 1, 0);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
       if (marks && mark) mark(ctx, 3);
       if (NDIM == 2 || P.logn <= 24)
         hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
