@@ -567,8 +567,7 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const bool big_ok = d->ndim == 2 && d->res_tol == 0.0 && d->n_min == 0 &&
                         !(d->flags & ATSFFT_FLAG_COMPENSATED) && Bbig <= (int64_t)kBigMax &&
                         d->alpha <= kSlabs && row_bytes <= kRowBytes &&
-                        big_cols_smem(d->dtype, (uint32_t)Bbig) <= prop.sharedMemPerBlock &&
-                        big_stats_smem((uint32_t)Bbig) <= prop.sharedMemPerBlock;
+                        big_cols_smem(d->dtype, (uint32_t)Bbig) <= prop.sharedMemPerBlock;
     if (!big_ok) {
       char msg[200];
       std::snprintf(msg, sizeof(msg),

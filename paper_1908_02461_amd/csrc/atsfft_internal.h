@@ -159,7 +159,6 @@ size_t residual_smem_bytes(int dtype, uint32_t Bc_max);
 size_t vote_smem_bytes(uint32_t L_loc, uint32_t Bc_max);
 size_t big_rows_smem(int dtype, uint32_t B);
 size_t big_cols_smem(int dtype, uint32_t B);
-size_t big_stats_smem(uint32_t B);
 // Device address of `device`'s fixed workspace (kScratchBytes), looked up once
 // per device; `device` must be the current device on the first call for it.
 hipError_t scratch_address(int device, void **ptr);

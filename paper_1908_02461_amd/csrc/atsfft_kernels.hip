@@ -1374,7 +1374,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   }
   const uint32_t logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
-  if (Bc > P.lds_cap) return;  // a large array: k_big_rows, k_big_cols, k_big_stats
+  if (Bc > P.lds_cap) return;  // a large array: k_big_rows, k_big_cols, the k_bs_* steps
   const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
   // what the statistics read from device memory, read before the bucket
   // stores below: a vector load after them would wait for every one of them
@@ -1891,6 +1891,26 @@ __device__ __forceinline__ BigArr<C> big_arr(const KParams &P, uint32_t sig, int
   return a;
 }
 
+constexpr uint32_t kBigChunk = 4096;
+constexpr uint32_t kBigThreads = 256;
+constexpr uint32_t kBigChunks = kBigMax * kBigMax / kBigChunk;
+struct BigStat {
+  unsigned long long kmin, kmax;      // extreme keys of m
+  unsigned long long pa, pb, mask;    // prefixes (of key - kmin) of the two searches, settled digits
+  uint32_t ka, kb;                    // their ranks within the prefixes
+  uint32_t n_above, n_ge, n_gt, nmax; // #{m > T}, #{m >= v}, #{m > v}; local maxima (probe)
+  uint32_t num, need, mode, pad;      // mode 1: J = {m > T}; 2: {m >= v}; 3: above v, then ties in order
+  double T, vcut;
+  uint32_t hist[2][256];
+  uint32_t ctake[kBigChunks], ctie[kBigChunks];  // per chunk: counts, then list positions and ties before
+};
+template <typename C> __device__ __forceinline__ BigStat *big_stat(const BigArr<C> &a) {
+  return reinterpret_cast<BigStat *>(a.y + 2 * a.pstride);
+}
+template <typename R> __device__ __forceinline__ R *big_m(const BigArr<typename CT<R>::C> &a) {
+  return reinterpret_cast<R *>(a.y + a.pstride);
+}
+
 // one workgroup per (bucket row b1, loop or level, signal)
 template <typename R>
 __global__ __launch_bounds__(256) void k_big_rows(KParams P, int role, int iter) {
@@ -1921,7 +1941,7 @@ template <typename R> constexpr uint32_t big_cols() { return sizeof(R) == 4 ? 16
 
 // one workgroup per (block of big_cols() columns, loop or level, signal)
 template <typename R>
-__global__ __launch_bounds__(256) void k_big_cols(KParams P, int role, int iter) {
+__global__ __launch_bounds__(1024) void k_big_cols(KParams P, int role, int iter) {
   using C = typename CT<R>::C;
   constexpr uint32_t CB = big_cols<R>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1932,6 +1952,12 @@ __global__ __launch_bounds__(256) void k_big_cols(KParams P, int role, int iter)
   if (!ar.ok || c0 >= ar.B) return;
   const uint32_t B = ar.B, logB = ilog2(B);
   C *y = ar.y;
+  if (blockIdx.x == 0) {
+    // the array's statistics record, in a partial slot the row pass has
+    // consumed: zero, with the smallest key at its largest value
+    uint32_t *w = reinterpret_cast<uint32_t *>(y + 2 * ar.pstride);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(BigStat) / 4); i += blockDim.x) w[i] = i < 2 ? ~0u : 0u;
+  }
   for (uint32_t i = threadIdx.x; i < B * CB; i += blockDim.x) {
     const uint32_t b1 = i / CB, c = i % CB;
     buf[lds_at<true>(bitrev(b1, logB) * CB + c)] = y[((size_t)b1 << logB) + c0 + c];
@@ -1944,32 +1970,63 @@ __global__ __launch_bounds__(256) void k_big_cols(KParams P, int role, int iter)
   }
 }
 
-// one 1024-thread workgroup per (location loop or probe level, signal): the
-// threshold of k_bucket, then (role 0) its top-num cutoff or (role 1) its
-// local-maximum count and the B-update rule for the level, over device memory
+// The statistics of a large array are spread over many workgroups, a launch
+// per step: a 256-thread workgroup per (4096-bucket chunk, array, signal), or
+// per (array, signal) for the picks and the end step.  An array's running
+// state is a BigStat record in a spare partial slot (slot 2; k_big_cols zeroes
+// it).  The steps: m = |y|^2 and its key range; per 8-bit digit a histogram
+// and a pick, for the noise floor's rank and, in location loops, the cutoff
+// value's rank Bc - num at once (as in k_bucket); the counts above T and at
+// or above the cutoff value (location) or the local maxima (probe); the
+// B-update rule (probe) or the cutoff's mode (location); then per chunk the
+// taken buckets' count, a scan over the chunks, and the list and bitmap.
+// The digit of rank k in a 256-bin histogram (LDS or device memory), uniform
+// over the calling wave; k becomes the rank within the digit's bin.
+__device__ __forceinline__ uint32_t wave_pick_digit(const uint32_t *h, uint32_t &k) {
+  const uint32_t l = threadIdx.x & 63u;
+  const uint32_t c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
+  const uint32_t s = c0 + c1 + c2 + c3;
+  const uint32_t incl = wave_incl_scan(s), excl = incl - s;
+  const unsigned long long m = __ballot(excl <= k && k < incl);
+  const uint32_t src = m ? (uint32_t)__builtin_ctzll(m) : 0u;
+  uint32_t digit, run;
+  if (k < excl + c0) {
+    digit = 4 * l;
+    run = excl;
+  } else if (k < excl + c0 + c1) {
+    digit = 4 * l + 1;
+    run = excl + c0;
+  } else if (k < excl + c0 + c1 + c2) {
+    digit = 4 * l + 2;
+    run = excl + c0 + c1;
+  } else {
+    digit = 4 * l + 3;
+    run = excl + c0 + c1 + c2;
+  }
+  k = lane_value(k - run, src);
+  return lane_value(digit, src);
+}
+
+// the chunk of a (chunk, array, signal) workgroup, or false when it has none
+template <typename C>
+__device__ __forceinline__ bool big_chunk(const KParams &P, int role, int iter, BigArr<C> &ar, uint32_t &b0) {
+  ar = big_arr<C>(P, blockIdx.z, role, (uint32_t)iter + blockIdx.y);
+  b0 = blockIdx.x * kBigChunk;
+  return ar.ok && b0 < ar.B * ar.B;
+}
+
 template <typename R>
-__global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int role, int iter) {
+__global__ __launch_bounds__(kBigThreads) void k_bs_m(KParams P, int role, int iter) {
   using C = typename CT<R>::C;
   using K = typename CT<R>::K;
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem);  // 512 words
-  uint32_t *sh = hist + 512;                             // 32 words
-  K *wk = reinterpret_cast<K *>(sh + 32);                // 2 keys per wave
-  uint32_t *cg = reinterpret_cast<uint32_t *>(wk + 2 * (kBucketThreads / 64));  // per-chunk counts
-  const uint32_t idx = (uint32_t)iter + blockIdx.x, sig = blockIdx.y;
-  const BigArr<C> ar = big_arr<C>(P, sig, role, idx);
-  if (!ar.ok) return;
-  SigState *st = state_of(P, sig);
-  const int32_t khat_in = st->khat;  // read before the m stores below
-  const uint32_t B = ar.B, logB = ilog2(B);
-  const uint32_t Bc = B * B, nch = Bc >> 6;
-  uint32_t *ce = cg + nch;
-  const uint32_t tid = threadIdx.x, T = blockDim.x, lane = tid & 63u, wave = tid >> 6, nw = T >> 6;
-  const C *y = ar.y;
-  R *m = reinterpret_cast<R *>(ar.y + (role == 0 ? (size_t)P.Bc_max : (size_t)Bc));  // a spare partial slot
+  __shared__ K wk[2 * (kBigThreads / 64)];
+  BigArr<C> ar;
+  uint32_t b0;
+  if (!big_chunk(P, role, iter, ar, b0)) return;
+  R *m = big_m<R>(ar);
   K kmax = 0, kmin = ~(K)0;
-  for (uint32_t b = tid; b < Bc; b += T) {
-    const C v = y[b];
+  for (uint32_t b = b0 + threadIdx.x; b < b0 + kBigChunk; b += kBigThreads) {
+    const C v = ar.y[b];
     const R mb = v.x * v.x + v.y * v.y;
     m[b] = mb;
     kmax = max(kmax, key_of(mb));
@@ -1977,29 +2034,155 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
   }
   kmax = wave_extreme<true>(kmax);
   kmin = wave_extreme<false>(kmin);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   if (lane == 0) {
     wk[2 * wave] = kmax;
     wk[2 * wave + 1] = kmin;
   }
   __syncthreads();
-  kmax = wave_extreme<true>(lane < nw ? wk[2 * lane] : (K)0);
-  kmin = wave_extreme<false>(lane < nw ? wk[2 * lane + 1] : ~(K)0);
-  // threshold: as k_bucket (noise floor from the floor(q (Bc-1))-th order
-  // statistic, c_noise = ln(Bc / noise_rate), relative floor rho * max m)
-  const R mmax = val_of(kmax);
-  const uint32_t qi = (uint32_t)floor(P.q * (double)(Bc - 1));
-  const R floor_m = block_kth_smallest<R>(m, Bc, qi, hist, sh, (R)-1, kmin, kmax);
-  const double c_noise = log((double)Bc / P.noise_rate);
-  const double t1 = c_noise * ((double)floor_m / P.neg_log1mq);
-  const double t2 = P.rho * (double)mmax;
-  const double Td = t1 > t2 ? t1 : t2;
-  const R Tr = (R)Td;
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < kBigThreads / 64; ++w) {
+      kmax = max(kmax, wk[2 * w]);
+      kmin = min(kmin, wk[2 * w + 1]);
+    }
+    BigStat *bs = big_stat(ar);
+    atomicMax(&bs->kmax, (unsigned long long)kmax);
+    atomicMin(&bs->kmin, (unsigned long long)kmin);
+  }
+}
 
-  if (role == 1) {
+// the digit pass `pass` of an array: its top bit, width and shift (width 0:
+// the selection is complete)
+template <typename K>
+__device__ __forceinline__ int big_pass(const BigStat *bs, int pass, int &shift) {
+  const K lo = (K)bs->kmin, hi = (K)bs->kmax;
+  const int nbits = hi > lo ? bit_length(hi - lo) : 1;
+  const int top = nbits - 8 * pass;
+  const int width = top <= 0 ? 0 : (top < 8 ? top : 8);
+  shift = top - width;
+  return width;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBigThreads) void k_bs_hist(KParams P, int role, int iter, int pass) {
+  using C = typename CT<R>::C;
+  using K = typename CT<R>::K;
+  __shared__ uint32_t h[512];
+  BigArr<C> ar;
+  uint32_t b0;
+  if (!big_chunk(P, role, iter, ar, b0)) return;
+  BigStat *bs = big_stat(ar);
+  int shift;
+  const int width = big_pass<K>(bs, pass, shift);
+  if (width == 0) return;
+  const uint32_t dmask = (1u << width) - 1u;
+  const K lo = (K)bs->kmin, pa = (K)bs->pa, pb = (K)bs->pb, mask = (K)bs->mask;
+  const bool two = role == 0;
+  for (uint32_t i = threadIdx.x; i < 512; i += kBigThreads) h[i] = 0;
+  __syncthreads();
+  const R *m = big_m<R>(ar);
+  for (uint32_t b = b0 + threadIdx.x; b < b0 + kBigChunk; b += kBigThreads) {
+    const K key = key_of(m[b]) - lo, kp = key & mask;
+    const uint32_t bin = (uint32_t)(key >> shift) & dmask;
+    if (kp == pa)
+      atomicAdd(&h[bin], 1u);
+    else if (two && kp == pb)
+      atomicAdd(&h[256 + bin], 1u);
+  }
+  __syncthreads();
+  uint32_t *g = &bs->hist[0][0];
+  for (uint32_t i = threadIdx.x; i < 512; i += kBigThreads)
+    if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+// one workgroup of two waves per (array, signal): wave 0 picks the noise
+// floor's digit, wave 1 (location loops) the cutoff value's; after the last
+// digit the threshold T and the cutoff value
+template <typename R>
+__global__ __launch_bounds__(128) void k_bs_pick(KParams P, int role, int iter, int pass) {
+  using C = typename CT<R>::C;
+  using K = typename CT<R>::K;
+  const uint32_t sig = blockIdx.y, idx = (uint32_t)iter + blockIdx.x;
+  const BigArr<C> ar = big_arr<C>(P, sig, role, idx);
+  if (!ar.ok) return;
+  BigStat *bs = big_stat(ar);
+  int shift;
+  const int width = big_pass<K>(bs, pass, shift);
+  if (width == 0) return;
+  const uint32_t dmask = (1u << width) - 1u;
+  const uint32_t Bc = ar.B * ar.B;
+  uint32_t ka = bs->ka, kb = bs->kb, num = bs->num;
+  if (pass == 0) {
+    ka = (uint32_t)floor(P.q * (double)(Bc - 1));
+    num = 0;
+    if (role == 0) {
+      num = (uint32_t)P.d * (uint32_t)max(state_of(P, sig)->khat, 0);
+      if (num > Bc) num = Bc;
+    }
+    kb = num > 0 ? Bc - num : 0u;
+  }
+  const K lo = (K)bs->kmin, pa = (K)bs->pa, pb = (K)bs->pb;
+  const bool second = threadIdx.x >= 64;
+  uint32_t digit = 0, k = second ? kb : ka;
+  if (!second || role == 0) digit = wave_pick_digit(second && pa != pb ? bs->hist[1] : bs->hist[0], k);
+  __syncthreads();  // both waves have read the histograms
+  uint32_t *g = &bs->hist[0][0];
+  for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) g[i] = 0;
+  if ((threadIdx.x & 63u) == 0) {
+    if (!second) {
+      const K p = pa | ((K)digit << shift);
+      bs->pa = p;
+      bs->ka = k;
+      bs->mask = bs->mask | ((unsigned long long)dmask << shift);
+      bs->num = num;
+      if (shift == 0) {
+        // threshold as in k_bucket
+        const double floor_m = (double)val_of((K)(p + lo));
+        const double c_noise = log((double)Bc / P.noise_rate);
+        const double t1 = c_noise * (floor_m / P.neg_log1mq);
+        const double t2 = P.rho * (double)val_of((K)bs->kmax);
+        bs->T = t1 > t2 ? t1 : t2;
+      }
+    } else if (role == 0) {
+      const K p = pb | ((K)digit << shift);
+      bs->pb = p;
+      bs->kb = k;
+      if (shift == 0) bs->vcut = (double)val_of((K)(p + lo));
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBigThreads) void k_bs_count(KParams P, int role, int iter) {
+  using C = typename CT<R>::C;
+  __shared__ uint32_t sh[16];
+  BigArr<C> ar;
+  uint32_t b0;
+  if (!big_chunk(P, role, iter, ar, b0)) return;
+  BigStat *bs = big_stat(ar);
+  const R *m = big_m<R>(ar);
+  const R Tr = (R)bs->T;
+  if (role == 0) {
+    const R v = (R)bs->vcut;
+    uint32_t a = 0, g = 0, t = 0;
+    for (uint32_t b = b0 + threadIdx.x; b < b0 + kBigChunk; b += kBigThreads) {
+      const R mb = m[b];
+      a += mb > Tr ? 1u : 0u;
+      g += mb >= v ? 1u : 0u;
+      t += mb > v ? 1u : 0u;
+    }
+    const uint32_t ag = block_sum(a | (g << 16), sh), tt = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+      atomicAdd(&bs->n_above, ag & 0xFFFFu);
+      atomicAdd(&bs->n_ge, ag >> 16);
+      atomicAdd(&bs->n_gt, tt);
+    }
+  } else {
     // local maxima among significant buckets, the 8-neighbourhood on the
     // torus, strict on the key (m, -index)
+    const uint32_t B = ar.B, logB = ilog2(B);
     uint32_t c = 0;
-    for (uint32_t b = tid; b < Bc; b += T) {
+    for (uint32_t b = b0 + threadIdx.x; b < b0 + kBigChunk; b += kBigThreads) {
       if (!(m[b] > Tr)) continue;
       const uint32_t r = b >> logB, q = b & (B - 1u);
       bool is_max = true;
@@ -2011,85 +2194,144 @@ __global__ __launch_bounds__(kBucketThreads) void k_big_stats(KParams P, int rol
         }
       c += is_max ? 1u : 0u;
     }
-    const uint32_t k = block_sum(c, &sh[4]);
-    if (tid == 0) {
-      ProbeRec *h = hist_of(P, sig) + idx;
-      h->B = (int32_t)B;
-      h->dec = 0;
-      h->T = Td;
-      if ((int32_t)idx != P.probe_drop)
-        __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // a large level is a round of its own: this workgroup applies the rule
-      probe_control<2>(P, sig, (int)idx, (int)idx + 1);
-    }
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) atomicAdd(&bs->nmax, c);
+  }
+}
+
+// one thread per (array, signal): the probe level's count and its B-update
+// rule (a large level is a round of its own), or the location loop's T and
+// cutoff mode
+template <typename R>
+__global__ __launch_bounds__(64) void k_bs_end(KParams P, int role, int iter) {
+  using C = typename CT<R>::C;
+  if (threadIdx.x != 0) return;
+  const uint32_t sig = blockIdx.y, idx = (uint32_t)iter + blockIdx.x;
+  const BigArr<C> ar = big_arr<C>(P, sig, role, idx);
+  if (!ar.ok) return;
+  BigStat *bs = big_stat(ar);
+  if (role == 1) {
+    ProbeRec *h = hist_of(P, sig) + idx;
+    h->B = (int32_t)ar.B;
+    h->dec = 0;
+    h->T = bs->T;
+    if ((int32_t)idx != P.probe_drop)
+      __hip_atomic_store(&h->k, (int32_t)bs->nmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    probe_control<2>(P, sig, (int)idx, (int)idx + 1);
     return;
   }
+  tloc_of(P, sig)[idx] = bs->T;
+  const uint32_t num = bs->num;
+  const bool fits = bs->n_above <= num;
+  bs->mode = fits ? 1u : (bs->n_ge == num && !P.cut_ties ? 2u : 3u);
+  bs->need = fits ? 0u : num - bs->n_gt;
+}
 
-  if (tid == 0) tloc_of(P, sig)[idx] = Td;
-  uint32_t above = 0;
-  for (uint32_t b = tid; b < Bc; b += T) above += m[b] > Tr ? 1u : 0u;
-  const uint32_t n_above = block_sum(above, &sh[4]);
-  uint32_t num = (uint32_t)P.d * (uint32_t)max(khat_in, 0);
-  if (num > Bc) num = Bc;
-  R v = Tr;
-  uint32_t need = 0;
-  if (n_above > num) {
-    v = block_kth_smallest<R>(m, Bc, n_above - num, hist, sh, Tr);
-    uint32_t gt = 0;
-    for (uint32_t b = tid; b < Bc; b += T) gt += m[b] > v ? 1u : 0u;
-    need = num - block_sum(gt, &sh[4]);
+// location loops: the buckets of a chunk the cutoff takes (J) and, in mode 3,
+// those equal to the cutoff value v (of which the first `need` are taken)
+template <typename R>
+__device__ __forceinline__ void big_take(const BigStat *bs, R mb, bool &f0, bool &eq) {
+  const uint32_t mode = bs->mode;
+  const R v = mode == 1 ? (R)bs->T : (R)bs->vcut;
+  f0 = mode == 2 ? mb >= v : mb > v;
+  eq = mode == 3 && mb == v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBigThreads) void k_bs_chunks(KParams P, int iter) {
+  using C = typename CT<R>::C;
+  __shared__ uint32_t sh[16];
+  BigArr<C> ar;
+  uint32_t b0;
+  if (!big_chunk(P, 0, iter, ar, b0)) return;
+  BigStat *bs = big_stat(ar);
+  const R *m = big_m<R>(ar);
+  uint32_t g = 0, e = 0;
+  for (uint32_t b = b0 + threadIdx.x; b < b0 + kBigChunk; b += kBigThreads) {
+    bool f0, eq;
+    big_take<R>(bs, m[b], f0, eq);
+    g += f0 ? 1u : 0u;
+    e += eq ? 1u : 0u;
   }
-  // per 64-bucket chunk: buckets above v and buckets equal to v (a wave a chunk)
-  for (uint32_t c = wave; c < nch; c += nw) {
-    const R mb = m[(c << 6) + lane];
-    const unsigned long long g = __ballot(mb > v);
-    const unsigned long long e = __ballot(need > 0u && mb == v);
-    if (lane == 0) {
-      cg[c] = (uint32_t)__popcll(g);
-      ce[c] = (uint32_t)__popcll(e);
-    }
+  const uint32_t ge = block_sum(g | (e << 16), sh);
+  if (threadIdx.x == 0) {
+    bs->ctake[blockIdx.x] = ge & 0xFFFFu;
+    bs->ctie[blockIdx.x] = ge >> 16;
   }
-  __syncthreads();
-  // scans over the chunks (a thread a run of consecutive chunks): ties before
-  // each chunk, then its first list position (the first `need` ties are taken)
-  const uint32_t per = (nch + T - 1) / T, c_lo = tid * per, c_hi = min(c_lo + per, nch);
-  uint32_t es = 0;
-  for (uint32_t c = c_lo; c < c_hi; ++c) es += ce[c];
-  uint32_t te = block_excl_scan(es, sh);
-  uint32_t ss = 0;
-  for (uint32_t c = c_lo; c < c_hi; ++c) {
-    const uint32_t sel = cg[c] + min(ce[c], need > te ? need - te : 0u);
-    te += ce[c];
-    ss += sel;
-  }
+}
+
+// one workgroup per (array, signal), a thread per chunk: ties before each
+// chunk, then its first list position (the first `need` ties are taken)
+template <typename R>
+__global__ __launch_bounds__(kBigChunks) void k_bs_scan(KParams P, int iter) {
+  using C = typename CT<R>::C;
+  __shared__ uint32_t sh[32];
+  const uint32_t sig = blockIdx.y, idx = (uint32_t)iter + blockIdx.x;
+  const BigArr<C> ar = big_arr<C>(P, sig, 0, idx);
+  if (!ar.ok) return;
+  BigStat *bs = big_stat(ar);
+  const uint32_t nch = ar.B * ar.B / kBigChunk, t = threadIdx.x, need = bs->need;
+  const uint32_t take = t < nch ? bs->ctake[t] : 0u, tie = t < nch ? bs->ctie[t] : 0u;
+  const uint32_t te = block_excl_scan(tie, sh);
+  const uint32_t sel = take + min(tie, need > te ? need - te : 0u);
   uint32_t total;
-  uint32_t pos = block_excl_scan(ss, sh, &total);
-  te -= es;  // back to the ties before this thread's first chunk
-  for (uint32_t c = c_lo; c < c_hi; ++c) {
-    const uint32_t sel = cg[c] + min(ce[c], need > te ? need - te : 0u);
-    const uint32_t e0 = te;
-    te += ce[c];
-    cg[c] = pos;
-    ce[c] = e0;
-    pos += sel;
+  const uint32_t pos = block_excl_scan(sel, sh, &total);
+  if (t < nch) {
+    bs->ctake[t] = pos;
+    bs->ctie[t] = te;
   }
-  __syncthreads();
-  int32_t *jl = jlist_of(P, sig, idx);
-  uint32_t *jb = jbits_of(P, sig, idx);
-  for (uint32_t c = wave; c < nch; c += nw) {
-    const uint32_t b = (c << 6) + lane;
-    const R mb = m[b];
-    const bool eq = need > 0u && mb == v;
-    const unsigned long long e = __ballot(eq);
-    const bool f = mb > v || (eq && ce[c] + lanes_below(e) < need);
-    const unsigned long long fm = __ballot(f);
-    if (f) jl[cg[c] + lanes_below(fm)] = (int32_t)b;
+  if (t == 0) jcount_of(P, sig)[idx] = (int32_t)total;
+}
+
+// per chunk: the list in index order and the bitmap, a 64-bucket run per
+// ballot (a wave takes 16 consecutive runs)
+template <typename R>
+__global__ __launch_bounds__(kBigThreads) void k_bs_list(KParams P, int iter) {
+  using C = typename CT<R>::C;
+  __shared__ uint32_t sg[64], se[64];
+  BigArr<C> ar;
+  uint32_t b0;
+  if (!big_chunk(P, 0, iter, ar, b0)) return;
+  const BigStat *bs = big_stat(ar);
+  const R *m = big_m<R>(ar);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, need = bs->need;
+  for (uint32_t r = wave; r < 64; r += kBigThreads / 64) {
+    const uint32_t b = b0 + 64 * r + lane;
+    bool f0, eq;
+    big_take<R>(bs, m[b], f0, eq);
+    const unsigned long long g = __ballot(f0), e = __ballot(eq);
     if (lane == 0) {
-      jb[2 * c] = (uint32_t)fm;
-      jb[2 * c + 1] = (uint32_t)(fm >> 32);
+      sg[r] = (uint32_t)__popcll(g);
+      se[r] = (uint32_t)__popcll(e);
     }
   }
-  if (tid == 0) jcount_of(P, sig)[idx] = (int32_t)total;
+  __syncthreads();
+  if (wave == 0) {
+    // the runs' ties before them and list positions, from the chunk's
+    const uint32_t tie0 = bs->ctie[blockIdx.x], pos0 = bs->ctake[blockIdx.x];
+    const uint32_t e = se[lane], g = sg[lane];
+    const uint32_t te = tie0 + wave_incl_scan(e) - e;
+    const uint32_t sel = g + min(e, need > te ? need - te : 0u);
+    const uint32_t pos = pos0 + wave_incl_scan(sel) - sel;
+    sg[lane] = pos;
+    se[lane] = te;
+  }
+  __syncthreads();
+  int32_t *jl = jlist_of(P, blockIdx.z, (uint32_t)iter + blockIdx.y);
+  uint32_t *jb = jbits_of(P, blockIdx.z, (uint32_t)iter + blockIdx.y);
+  for (uint32_t r = wave; r < 64; r += kBigThreads / 64) {
+    const uint32_t b = b0 + 64 * r + lane;
+    bool f0, eq;
+    big_take<R>(bs, m[b], f0, eq);
+    const unsigned long long e = __ballot(eq);
+    const bool f = f0 || (eq && se[r] + lanes_below(e) < need);
+    const unsigned long long fm = __ballot(f);
+    if (f) jl[sg[r] + lanes_below(fm)] = (int32_t)b;
+    if (lane == 0) {
+      jb[(b0 >> 5) + 2 * r] = (uint32_t)fm;
+      jb[(b0 >> 5) + 2 * r + 1] = (uint32_t)(fm >> 32);
+    }
+  }
 }
 
 // -------------------------------------------------------------- k_vote ----
@@ -2140,7 +2382,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
   // workgroup work items: selected buckets, or in 2D rounds of KB x KB blocks
   const bool blocks2 = NDIM == 2 && logW >= 2u;
-  const uint32_t items = blocks2 ? ((ncand << (2u * (logW - 2u))) + blockDim.x - 1u) / blockDim.x : ncand;
+  // otherwise (bucket, preimage) pairs, K per thread
+  const uint32_t logPer = NDIM == 1 ? logW : 2u * logW;
+  const uint32_t items = blocks2 ? ((ncand << (2u * (logW - 2u))) + blockDim.x - 1u) / blockDim.x
+                                 : ((ncand << logPer) + (uint32_t)K * blockDim.x - 1u) / ((uint32_t)K * blockDim.x);
   if (blockIdx.x >= items) return;
   const uint32_t L = P.L_loc, Tv = P.T_vote;
   const uint32_t words = (Bc + 31) >> 5;
@@ -2302,38 +2547,41 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
     return;
   }
 
-  const uint32_t per = NDIM == 1 ? W : W * W;  // candidates per selected bucket
-  for (uint32_t jj = blockIdx.x; jj < ncand; jj += gridDim.x) {
-    const uint32_t j = (uint32_t)jl[jj];
-    const uint32_t p01 = ((NDIM == 1 ? j : (j >> logB)) << logW) - c;
-    const uint32_t p02 = ((j & (B - 1u)) << logW) - c;
-    for (uint32_t base = 0; base < per; base += K * T) {
-      // the block's candidates and their first nA tests
-      uint32_t f[K], v[K];
+  // every (selected bucket, preimage) pair, the buckets in list order: a
+  // block's K x T consecutive pairs may span several buckets (W may be as
+  // small as 2 per axis)
+  const uint32_t units = ncand << logPer;
+  for (uint32_t u0 = blockIdx.x * (uint32_t)K * T; u0 < units; u0 += gridDim.x * (uint32_t)K * T) {
+    // the block's candidates and their first nA tests
+    uint32_t f[K], v[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const uint32_t idx = base + threadIdx.x + (uint32_t)k * T;
-        v[k] = idx < per ? 0u : 0x80000000u;  // the high bit marks no candidate
-        if (NDIM == 1) {
-          f[k] = mulmod(inv0, (p01 + idx) & mask);
-        } else {
-          const uint32_t p1 = (p01 + (idx >> logW)) & mask;
-          const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
-          f[k] = (mulmod(inv0, p1) << logn) | mulmod(inv1, p2);
-        }
+    for (int k = 0; k < K; ++k) {
+      const uint32_t u = u0 + threadIdx.x + (uint32_t)k * T;
+      const bool real = u < units;
+      v[k] = real ? 0u : 0x80000000u;  // the high bit marks no candidate
+      const uint32_t j = (uint32_t)jl[real ? (u >> logPer) : 0u];
+      const uint32_t idx = u & ((1u << logPer) - 1u);
+      const uint32_t p01 = ((NDIM == 1 ? j : (j >> logB)) << logW) - c;
+      if (NDIM == 1) {
+        f[k] = mulmod(inv0, (p01 + idx) & mask);
+      } else {
+        const uint32_t p02 = ((j & (B - 1u)) << logW) - c;
+        const uint32_t p1 = (p01 + (idx >> logW)) & mask;
+        const uint32_t p2 = (p02 + (idx & (W - 1u))) & mask;
+        f[k] = (mulmod(inv0, p1) << logn) | mulmod(inv1, p2);
       }
-      for (uint32_t m = 0; m < nA; ++m) {
-        const uint32_t l = other(m);
-        uint32_t h[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) h[k] = bucket(l, f[k]);
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += in_J(l, h[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) keep(f[k], v[k]);
-      drain();
     }
+    for (uint32_t m = 0; m < nA; ++m) {
+      const uint32_t l = other(m);
+      uint32_t h[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) h[k] = bucket(l, f[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] += in_J(l, h[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) keep(f[k], v[k]);
+    drain();
   }
 }
 
@@ -2997,7 +3245,6 @@ size_t big_cols_smem(int dtype, uint32_t B) {
   const size_t cs = dtype == 0 ? 8 : 16, e = (size_t)B * (dtype == 0 ? 16 : 8);
   return cs * (e + e / 32);
 }
-size_t big_stats_smem(uint32_t B) { return 4 * (512 + 32) + 8 * 2 * (kBucketThreads / 64) + 8 * ((size_t)B * B / 64); }
 
 size_t estimate_smem_bytes(uint32_t max_out) {
   uint32_t p2 = 1;
@@ -3038,9 +3285,6 @@ template <typename R, int NDIM> static hipError_t set_smem(size_t bucket, size_t
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_big_cols<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)big_cols_smem(dt, kBigMax));
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_big_stats<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)big_stats_smem(kBigMax));
-    if (e != hipSuccess) return e;
   }
   for (const void *f : {reinterpret_cast<const void *>(&k_vote<NDIM, true>),
                         reinterpret_cast<const void *>(&k_vote<NDIM, false>)}) {
@@ -3072,6 +3316,28 @@ static uint32_t ilog2_host_u32(uint32_t v) {
   return r;
 }
 
+// The statistics steps of the large arrays of a launch: `arrays` of them per
+// signal from index `iter` (role 0: the location loops; role 1: one probe
+// level) with at most `chunks` 4096-bucket chunks each.
+template <typename R>
+static void big_stats(const KParams &P, int role, int iter, uint32_t arrays, uint32_t chunks, int batch,
+                      hipStream_t s) {
+  const dim3 cg(chunks, arrays, batch), ag(arrays, batch);
+  hipLaunchKernelGGL((k_bs_m<R>), cg, dim3(kBigThreads), 0, s, P, role, iter);
+  const int passes = sizeof(R) == 4 ? 4 : 8;  // 8-bit digits of the key range
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL((k_bs_hist<R>), cg, dim3(kBigThreads), 0, s, P, role, iter, p);
+    hipLaunchKernelGGL((k_bs_pick<R>), ag, dim3(128), 0, s, P, role, iter, p);
+  }
+  hipLaunchKernelGGL((k_bs_count<R>), cg, dim3(kBigThreads), 0, s, P, role, iter);
+  hipLaunchKernelGGL((k_bs_end<R>), ag, dim3(64), 0, s, P, role, iter);
+  if (role == 0) {
+    hipLaunchKernelGGL((k_bs_chunks<R>), cg, dim3(kBigThreads), 0, s, P, iter);
+    hipLaunchKernelGGL((k_bs_scan<R>), ag, dim3(kBigChunks), 0, s, P, iter);
+    hipLaunchKernelGGL((k_bs_list<R>), cg, dim3(kBigThreads), 0, s, P, iter);
+  }
+}
+
 template <typename R, int NDIM, bool DEV = false>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, min(P.Bc_max, P.lds_cap));
@@ -3093,14 +3359,17 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
         // DFT, threshold, local maxima and B-update rule in device memory
         const uint32_t Bl = P.B0 << lo;
         const int dt = sizeof(R) == 4 ? 0 : 1;
-        const uint32_t slots = max(1u, min(P.tile_slots, (Bl * Bl + kTile - 1) / kTile));
+        // a large level has tiles for far more than tile_slots workgroups:
+        // about four per CU over the batch
+        KParams Qp = P;
+        Qp.tile_slots = max(P.tile_slots, 4u * P.n_cu / (uint32_t)batch);
+        const uint32_t slots = max(1u, min(Qp.tile_slots, (Bl * Bl + kTile - 1) / kTile));
         hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(slots, 1, batch), dim3(kHashThreads), 0, s,
-                           P, (int)lo, (int)lo + 1);
+                           Qp, (int)lo, (int)lo + 1);
         hipLaunchKernelGGL((k_big_rows<R>), dim3(Bl, 1, batch), dim3(256), big_rows_smem(dt, Bl), s, P, 1, (int)lo);
-        hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bl / big_cols<R>()), 1, batch), dim3(256),
+        hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bl / big_cols<R>()), 1, batch), dim3(1024),
                            big_cols_smem(dt, Bl), s, P, 1, (int)lo);
-        hipLaunchKernelGGL((k_big_stats<R>), dim3(1, batch), dim3(kBucketThreads), big_stats_smem(Bl), s, P, 1,
-                           (int)lo);
+        big_stats<R>(P, 1, (int)lo, 1, max(1u, Bl * Bl / kBigChunk), batch, s);
         ++lo;
         continue;
       }
@@ -3168,9 +3437,9 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
         hipLaunchKernelGGL((k_hash2d_stream<R, 16>), sgrid, dim3(kHashThreads), rb, s, Q);
       if (marks && mark) mark(ctx, 2);
       hipLaunchKernelGGL((k_big_rows<R>), dim3(Bb, loops, batch), dim3(256), big_rows_smem(dt, Bb), s, Q, 0, 0);
-      hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bb / big_cols<R>()), loops, batch), dim3(256),
+      hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bb / big_cols<R>()), loops, batch), dim3(1024),
                          big_cols_smem(dt, Bb), s, Q, 0, 0);
-      hipLaunchKernelGGL((k_big_stats<R>), dim3(P.L_loc, batch), dim3(kBucketThreads), big_stats_smem(Bb), s, Q, 0, 0);
+      big_stats<R>(Q, 0, 0, P.L_loc, max(1u, Bb * Bb / kBigChunk), batch, s);
       hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
       if (marks && mark) mark(ctx, 3);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, Q);
