@@ -3349,6 +3349,10 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
     // rounds of probe levels: every level up to B = probe_first at once, then
     // probe_step levels per round
     uint32_t lo = 0;
+    // probe levels have few tiles per signal: about four workgroups per CU
+    // over the batch (levels with fewer tiles take one slot per tile)
+    KParams Qp = P;
+    Qp.tile_slots = max(P.tile_slots, 4u * P.n_cu / (uint32_t)batch);
     auto level_bc = [&](uint32_t l) -> uint64_t {
       const uint64_t Bl = (uint64_t)P.B0 << l;
       return NDIM == 1 ? Bl : Bl * Bl;
@@ -3359,10 +3363,6 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
         // DFT, threshold, local maxima and B-update rule in device memory
         const uint32_t Bl = P.B0 << lo;
         const int dt = sizeof(R) == 4 ? 0 : 1;
-        // a large level has tiles for far more than tile_slots workgroups:
-        // about four per CU over the batch
-        KParams Qp = P;
-        Qp.tile_slots = max(P.tile_slots, 4u * P.n_cu / (uint32_t)batch);
         const uint32_t slots = max(1u, min(Qp.tile_slots, (Bl * Bl + kTile - 1) / kTile));
         hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(slots, 1, batch), dim3(kHashThreads), 0, s,
                            Qp, (int)lo, (int)lo + 1);
@@ -3379,19 +3379,19 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hi = min(hi, P.probe_levels);
       while (hi > lo + 1 && level_bc(hi - 1) > P.lds_cap) --hi;  // k_bucket rounds hold LDS-sized levels only
       // (level, slot) pairs: each level as many slots as it has tiles, at
-      // most tile_slots (so that small levels launch no idle workgroups)
+      // most Qp.tile_slots (so that small levels launch no idle workgroups)
       uint32_t slots = 0;
       for (uint32_t l = lo; l < hi; ++l) {
         const uint32_t Bl = P.B0 << l;
-        slots += max(1u, min(P.tile_slots, ((NDIM == 1 ? Bl : Bl * Bl) + kTile - 1) / kTile));
+        slots += max(1u, min(Qp.tile_slots, ((NDIM == 1 ? Bl : Bl * Bl) + kTile - 1) / kTile));
       }
       const uint32_t kProbeSlabs = NDIM == 1 ? P.probe_slabs : 1u;
       if (sizeof(R) == 4 && P.comp)
         hipLaunchKernelGGL((k_hash<R, NDIM, 1, sizeof(R) == 4, false, DEV>), dim3(kProbeSlabs * slots, 1, batch),
-                           dim3(kHashThreads), 0, s, P, (int)lo, (int)hi);
+                           dim3(kHashThreads), 0, s, Qp, (int)lo, (int)hi);
       else
         hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(kProbeSlabs * slots, 1, batch),
-                           dim3(kHashThreads), 0, s, P, (int)lo, (int)hi);
+                           dim3(kHashThreads), 0, s, Qp, (int)lo, (int)hi);
       hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
       lo = hi;
     }
