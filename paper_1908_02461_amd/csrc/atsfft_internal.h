@@ -11,6 +11,8 @@ constexpr int kMaxLoops = 32;        // L_loc, L_est <= 31
 constexpr int kMaxProbe = 32;        // P_max <= 32
 constexpr int kBucketThreads = 1024; // one workgroup per bucket array
 constexpr int kBucketMaxPer = 16;    // bucket values per thread: B^ndim <= 16384
+constexpr int kSmallBucketThreads = 256;  // k_bucket workgroups for arrays of at most kSmallBuckets
+constexpr uint32_t kSmallBuckets = 4096;
 constexpr int kHashThreads = 256;    // hash workgroup: 64 buckets x 4 wrap groups
 constexpr int kSlabs = 8;            // address slabs of a signal, one per XCD
 constexpr int kVoteThreads = 256;

@@ -1349,7 +1349,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t sig = blockIdx.y, loop = blockIdx.x;
-  if (main_phase == 2) {
+  if (main_phase >= 2) {
     // one linear grid, every signal's location loops first: their chain is
     // the longer, and when the grid takes several rounds of the chip the
     // short estimation loops then fill the last one
@@ -1375,6 +1375,10 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   const uint32_t logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
   if (Bc > P.lds_cap) return;  // a large array: k_big_rows, k_big_cols, the k_bs_* steps
+  // a main pass whose grid exceeds the chip runs arrays of at most
+  // kSmallBuckets in 256-thread workgroups, several to a CU, and the larger
+  // ones in a launch of their own (phase 3: the small class, 4: the large)
+  if ((main_phase == 3 && Bc > kSmallBuckets) || (main_phase == 4 && Bc <= kSmallBuckets)) return;
   const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
   // what the statistics read from device memory, read before the bucket
   // stores below: a vector load after them would wait for every one of them
@@ -3341,6 +3345,9 @@ static void big_stats(const KParams &P, int role, int iter, uint32_t arrays, uin
 template <typename R, int NDIM, bool DEV = false>
 static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark, void *ctx) {
   const size_t bsmem = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, min(P.Bc_max, P.lds_cap));
+  const size_t bsmem_small = bucket_smem_bytes(sizeof(R) == 4 ? 0 : 1, min(min(P.Bc_max, P.lds_cap), kSmallBuckets));
+  // the main k_bucket launches, one per class of array that can occur
+  const uint64_t bc_min = NDIM == 1 ? (uint64_t)P.B0 : (uint64_t)P.B0 * P.B0;
   const size_t esmem = estimate_smem_bytes(P.max_out);
   const uint32_t hash_blocks = kSlabs * max(1u, min(P.tile_slots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
@@ -3415,6 +3422,23 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const size_t rows_smem = std::max<size_t>((size_t)P.n * sizeof(typename CT<R>::C), 2 * kHashThreads * sizeof(R));
   const bool rows = !DEV && NDIM == 2 && P.rows2d_ok && !P.x_off && (reinterpret_cast<uintptr_t>(P.x) & 15u) == 0 && !P.comp;
   const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
+  // when the grid exceeds the chip (one 1024-thread workgroup per CU) the
+  // small arrays take 256-thread workgroups, several to a CU; otherwise
+  // every array a 1024-thread one (a chain of four waves is the longer)
+  const bool split = (uint64_t)loops * (uint64_t)batch > (uint64_t)P.n_cu;
+  const bool small_main = (P.fixed ? (uint64_t)P.Bc_max : bc_min) <= kSmallBuckets;
+  const bool large_main = min(P.Bc_max, P.lds_cap) > kSmallBuckets;
+  auto launch_main_bucket = [&](const KParams &Q) {
+    if (!split) {
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
+      return;
+    }
+    if (small_main)
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kSmallBucketThreads), bsmem_small, s, Q,
+                         3, 0);
+    if (large_main)
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 4, 0);
+  };
   auto main_pass = [&](const KParams &Q0, bool marks) {
     KParams Q = Q0;
     Q.est_wait = !DEV && (uint64_t)loops * (uint64_t)batch <= (uint64_t)P.n_cu ? 1u : 0u;
@@ -3440,7 +3464,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       hipLaunchKernelGGL((k_big_cols<R>), dim3(max(1u, Bb / big_cols<R>()), loops, batch), dim3(1024),
                          big_cols_smem(dt, Bb), s, Q, 0, 0);
       big_stats<R>(Q, 0, 0, P.L_loc, max(1u, Bb * Bb / kBigChunk), batch, s);
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
+      launch_main_bucket(Q);
       if (marks && mark) mark(ctx, 3);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV, true>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), 0, s, Q);
       hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads),
@@ -3470,7 +3494,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       else
         hipLaunchKernelGGL((k_hash<R, NDIM == 1 ? 1 : 1, 3, false, true, DEV>), hgrid, dim3(kHashThreads), 0, s, Q, 0, 0);
       if (marks && mark) mark(ctx, 2);
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 2, 0);
+      launch_main_bucket(Q);
       if (marks && mark) mark(ctx, 3);
       if (NDIM == 2 || P.logn <= 24)
         hipLaunchKernelGGL((k_vote<NDIM, true, DEV>), dim3(vote_blocks, E, batch), dim3(kVoteThreads), vsmem, s, Q);
