@@ -289,3 +289,24 @@ def test_cutoff_tie_path(A, monkeypatch, ndim, n, k, dt, snr, batch):
         assert np.array_equal(u["locs"], w["locs"]) and np.array_equal(u["vals"], w["vals"]), i
         tu, tw = plain.trace(a["ws"], i), ties.trace(b["ws"], i)
         assert np.array_equal(tu["J"], tw["J"]), i
+
+
+def test_main_grid_beyond_the_chip(A):
+    """A main pass with more bucket arrays than CUs (16 signals x 18 loops)
+    runs the arrays of at most 4096 buckets in 256-thread workgroups and the
+    larger ones in a 1024-thread launch of their own; sparsities from 8 to 300
+    at n = 2^18 give B* on both sides of 4096.  Every signal against the
+    oracle."""
+    import torch
+
+    n = 1 << 18
+    ks = [8, 16, 32, 64, 128, 200, 256, 300] * 2
+    plan = A.Plan(1, n, "c64", seed=23, max_batch=len(ks))
+    loops = plan.desc.L_loc + plan.desc.L_est
+    assert loops * len(ks) > torch.cuda.get_device_properties(0).multi_processor_count
+    xs = [synth.planted_1d(n, k, 700 + i, mag=("uniform", 0.5, 1.0), snr_db=30.0, dtype=np.complex64)[0]
+          for i, k in enumerate(ks)]
+    out, _ = _check_batch(A, plan, xs, "grid beyond the chip")
+    bstar = [plan.trace(out["ws"], i, full=False)["B_star"] for i in range(len(ks))]
+    print("B*", bstar, flush=True)
+    assert min(bstar) <= 4096 < max(bstar), bstar

@@ -138,3 +138,33 @@ def test_graph_replays_match_eager(A, how):
         _same_outputs(out, ref, len(ks), f"{how} replay {rep}")
         out["count"].fill_(-1)  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_device_lengths_grid_beyond_the_chip(A):
+    """24 signals x 18 loops: the device-length main pass runs its arrays
+    (all of at most 4096 buckets here) in 256-thread workgroups; the same as
+    the grouped execute, and each signal the oracle's."""
+    import torch
+
+    n_max = 1 << 16
+    ms = [1 << (12 + (i % 5)) for i in range(24)]
+    ks = [3 + (i * 7) % 20 for i in range(24)]
+    xs = [synth.planted_1d(m, k, 800 + i, mag=("uniform", 0.5, 1.0), snr_db=35.0, dtype=np.complex64)[0]
+          for i, (m, k) in enumerate(zip(ms, ks))]
+    ns = np.array(ms, dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    x = torch.from_numpy(np.concatenate(xs)).cuda()
+    plan = A.Plan(1, n_max, "c64", seed=19, n_min=1 << 12, max_batch=len(ms))
+    loops = plan.desc.L_loc + plan.desc.L_est
+    assert loops * len(ms) > torch.cuda.get_device_properties(0).multi_processor_count
+    print(f"device-length call beyond the chip: {len(ms)} signals", flush=True)
+    dev = plan.execute_uneven_dev(x, torch.from_numpy(offs).cuda(), torch.from_numpy(ns).cuda())
+    grp = plan.execute_uneven(x, offs, ns)
+    torch.cuda.synchronize()
+    _same_outputs(dev, grp, len(ms), "device vs grouped")
+    for i, (xi, m) in enumerate(zip(xs, ms)):
+        res = plan.results(dev, i)
+        ref = oracle.atsfft(xi.astype(np.complex128), sub_params(plan.desc, int(m), i), trace=False)
+        assert (res["status"], res["khat"], res["count"]) == (ref["status"], ref["khat"], ref["count"]), i
+        assert np.array_equal(res["locs"], ref["locs"]), i
+        assert value_rel_err(res["vals"], ref["vals"], "c64") < VAL_TOL["c64"], i
