@@ -90,6 +90,15 @@ def hash_kernel_sha256():
     return section_sha256("k_hash", "LDS FFT")
 
 
+def hash_launch_sha256():
+    """SHA-256 of the kernel-source lines that size the main-loop hash grid
+    (its tile slots per address slab), which the traffic also depends on."""
+    import hashlib
+
+    src = open(KERNEL_SRC).read().splitlines(keepends=True)
+    return hashlib.sha256("".join(ln for ln in src if "main_slots" in ln or "hash_blocks =" in ln).encode()).hexdigest()
+
+
 def measured_traffic(batch, path=None, sha=None, key="k_hash_source_sha256"):
     """HBM bytes per launch from a committed counter summary (default: the 1D
     main-loop k_hash), if it was taken on the current source section and
@@ -102,6 +111,8 @@ def measured_traffic(batch, path=None, sha=None, key="k_hash_source_sha256"):
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
         if kv.get(key) != (sha or hash_kernel_sha256()) or int(kv.get("batch", -1)) != batch:
+            return None
+        if path is None and kv.get("k_hash_launch_sha256") != hash_launch_sha256():
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

@@ -29,7 +29,8 @@ struct atsfft_plan_s {
   void *Ghat_dev;    // G'(o) tables, plan precision
   int64_t tab_host[128];  // element offsets by log2 B (passed in the kernel arguments)
   size_t bucket_smem, est_smem, bwd_smem;
-  uint32_t tile_slots;  // hash workgroups per slab and loop
+  uint32_t tile_slots;  // probe hash workgroups per slab and level, at most
+  uint32_t main_slots;  // main-pass hash workgroups per slab and loop group
   uint32_t hash_loops;  // main-pass loops per hash workgroup
   uint32_t vote_blocks; // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;   // 2D main loops may be hashed by rows staged in LDS
@@ -310,8 +311,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.probe_spin = plan->probe_spin;
   P.probe_drop = plan->probe_drop;
   P.cut_ties = plan->cut_ties;
-  P.pad_kp = 0;
   P.tile_slots = plan->tile_slots;
+  P.main_slots = plan->main_slots;
   P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
   for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
@@ -492,6 +493,15 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->tile_slots = (uint32_t)v;
   }
+  // 0: by batch, 64 slots up to 32 signals, else 32 (measured at n = 2^22, batch
+  // 32, B* 2048 and 4096: 32, 48, 64 slots 420, 416, 413 us; on the uneven batch
+  // of 512 signals, most with few 64-bucket tiles, the idle slots cost more:
+  // 6.87 ms per call with 32, 7.33 with 64)
+  p->main_slots = 0;
+  if (const char *env = std::getenv("ATSFFT_MAIN_SLOTS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 64) p->main_slots = (uint32_t)v;
+  }
   p->vote_blocks = 0;  // by batch
   {
     const uint64_t row_bytes = (uint64_t)n * (d->dtype == ATSFFT_C64 ? 8 : 16);
@@ -536,7 +546,9 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 32) p->probe_step = (uint32_t)v;
   }
-  p->probe_slabs = kSlabs;
+  // 1D probe levels gather cold lines that few other gathers touch again: one
+  // slab (measured at n = 2^22, batch 32: probe 160 us against 168 with kSlabs)
+  p->probe_slabs = 1;
   if (const char *env = std::getenv("ATSFFT_PROBE_SLABS")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v == 1 || v == kSlabs) p->probe_slabs = (uint32_t)v;

@@ -85,7 +85,7 @@ struct KParams {
   uint32_t B0, B_max, alpha_probe, alpha;
   uint32_t L_loc, L_est, T_vote, P_max, d, gamma, max_out, fixed;
   uint32_t fixed_B, fixed_k;
-  uint32_t tile_slots;  // hash tile slots per slab
+  uint32_t tile_slots;  // probe hash: most tile slots per slab and level
   uint32_t hash_loops;  // main-pass loops per hash workgroup (1D: 1..3)
   uint32_t vote_blocks;  // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;    // 2D main-loop hash by rows allowed: 0 no, 1 per bucket row, 2 streamed (plan)
@@ -112,7 +112,7 @@ struct KParams {
   uint32_t est_wait;     // main k_bucket: estimation loops read their partials after the signal's
                          // location loops have (set for launches whose whole grid is resident)
   uint32_t cut_ties;     // test hook: location loops always take the tie-aware cutoff path
-  uint32_t pad_kp;
+  uint32_t main_slots;   // main-pass hash: tile slots (workgroups) per slab and loop group (0: by batch)
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision
   int64_t tab[128];    // [4][32] element offsets by log2 B: probe taps, main taps, main G'(o),
