@@ -310,3 +310,28 @@ def test_main_grid_beyond_the_chip(A):
     bstar = [plan.trace(out["ws"], i, full=False)["B_star"] for i in range(len(ks))]
     print("B*", bstar, flush=True)
     assert min(bstar) <= 4096 < max(bstar), bstar
+
+
+@pytest.mark.parametrize("slots", [1, 7, 32])
+def test_main_hash_slots_leave_results_bitwise(A, monkeypatch, slots):
+    """The main-loop hash's tile slots per address slab (ATSFFT_MAIN_SLOTS)
+    only spread the 64-bucket tiles over workgroups: every bucket's partial is
+    summed by one thread in the same wrap order, so the bucket DFTs, located
+    set and values are bitwise those of the default (64 slots at this batch),
+    for a signal with fewer tiles than slots and one with more (B* = 8192)."""
+    n = 1 << 18
+    ks = [40, 300]
+    xs = np.stack([synth.planted_1d(n, k, 900 + i, mag=("uniform", 0.5, 1.0), snr_db=30.0,
+                                    dtype=np.complex64)[0] for i, k in enumerate(ks)])
+    ref_plan = A.Plan(1, n, "c64", seed=31, max_batch=2)
+    ref = run_gpu(ref_plan, xs)
+    monkeypatch.setenv("ATSFFT_MAIN_SLOTS", str(slots))
+    plan = A.Plan(1, n, "c64", seed=31, max_batch=2)
+    out = run_gpu(plan, xs)
+    print("main slots", slots, [ref_plan.trace(ref["ws"], i, full=False)["B_star"] for i in range(2)], flush=True)
+    for i in range(2):
+        u, v = ref_plan.results(ref, i), plan.results(out, i)
+        assert (u["count"], u["khat"], u["status"]) == (v["count"], v["khat"], v["status"])
+        assert np.array_equal(u["locs"], v["locs"]) and np.array_equal(u["vals"], v["vals"])
+        tu, tv = ref_plan.trace(ref["ws"], i), plan.trace(out["ws"], i)
+        assert np.array_equal(tu["yhat"], tv["yhat"])
