@@ -416,7 +416,8 @@ __device__ __forceinline__ void select_regs(const float (&v)[NPER], uint32_t per
     for (int j = 0; j < NPER; ++j) {
       const uint32_t kp = key[j] & mask;
       const bool ma = kp == pa, mb = TWO && kp == pb;
-      if (__ballot(ma || mb) == 0) continue;
+      // slots past per (the same for the whole block) are skipped whole
+      if ((uint32_t)j >= per || __ballot(ma || mb) == 0) continue;
       const uint32_t bin = (key[j] >> shift) & dmask;
       if (ma)
         atomicAdd(&ha[bin], 1u);
@@ -1245,9 +1246,22 @@ __global__ __launch_bounds__(NT) void k_hash2d_stream(KParams P) {
 
 // ------------------------------------------------------- probe control ----
 
+// A probe level's local-maximum count.  Every workgroup of a round stores its
+// count before it counts itself in, so a count that still reads -1 (k_init's
+// value) is on its way; the wait is bounded, and -1 comes back if it gives up.
+__device__ __forceinline__ int32_t probe_count(const KParams &P, ProbeRec *h) {
+  int32_t k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t spin = 0; k < 0 && spin < P.probe_spin; ++spin) {
+    __builtin_amdgcn_s_sleep(2);
+    k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return k;
+}
+
 // The adaptive-B iteration (Sec. III-A, Algorithm 2) for probe levels
-// [lo, hi) of one signal, on the counts its k_bucket workgroups recorded (run
-// by the last of them to finish).  The
+// [lo, hi) of one signal, on the counts its k_bucket workgroups recorded,
+// kv[i - lo] (-1: a count that never arrived), run by one thread of the last
+// of them to finish.  The
 // probe starts at B0 and only doubles until it stops: a halving always lands
 // on a bucket count already probed (or below the occupancy guard, or below
 // B0) and ends the probe there, so iteration i always hashes at B0 * 2^i and
@@ -1257,23 +1271,21 @@ __global__ __launch_bounds__(NT) void k_hash2d_stream(KParams P) {
 // the first iteration double); a count is acted on only once B^ndim >=
 // gamma * k_i; keep stops at B; halve stops at B/2 (k-hat from B); doubling
 // past B_max stops (saturated); P_max iterations stop (not converged).
+// s0: the signal's state as the round found it (written only by this routine
+// and k_init, in earlier launches, so a copy read when the round's workgroup
+// started is current).
 template <int NDIM>
-__device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi) {
+__device__ void probe_control(const KParams &P, uint32_t sig, int lo, int hi, const int32_t *kv,
+                              const SigState &s0) {
   SigState *st = state_of(P, sig);
-  SigState s = *st;  // written only by this routine and k_init, in earlier launches
+  SigState s = s0;
   ProbeRec *hist = hist_of(P, sig);
   for (int i = lo; i < hi && !s.done; ++i) {
     ProbeRec *h = hist + i;
     const uint32_t B = (uint32_t)s.B;
     const uint32_t logB = ilog2(B);
     const long long Bc = NDIM == 1 ? (long long)B : (long long)B * B;
-    // every workgroup of the round stored its count before it counted itself
-    // in; a store still on its way reads as -1 (k_init's value) for a while
-    int k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (uint32_t spin = 0; k < 0 && spin < P.probe_spin; ++spin) {
-      __builtin_amdgcn_s_sleep(2);
-      k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const int k = kv[i - lo];
     if (k < 0) {
       // the count never arrived: the probe stops at the last level it acted
       // on (B_star and khat as that level left them; before level 0, B0 and
@@ -1363,8 +1375,10 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   SigState *st = state_of(P, sig);
   uint32_t B;
   C *yg;
+  SigState st0;  // probe role: the state as this round found it
   if (!main_phase) {
-    if (st->done || level >= P.probe_levels) return;
+    st0 = *st;
+    if (st0.done || level >= P.probe_levels) return;
     B = P.B0 << level;
     yg = yprobe_of<C>(P, sig, level);
   } else {
@@ -1668,6 +1682,14 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
       }
     }
     const uint32_t k = block_sum(c, &sh[4]);
+    if (tid >= 64) return;
+    // the last of the round's workgroups of this signal applies the rule;
+    // it reads only the counts, themselves atomics, so no fence (an
+    // agent-scope fence writes back and invalidates the L2).  A signal has
+    // as many workgroups in the round as it has levels in it (a shorter
+    // signal of an uneven batch may have fewer levels than the launch).
+    const uint32_t in_round = min((uint32_t)iter + gridDim.x, P.probe_levels) - (uint32_t)iter;
+    uint32_t last = 0;
     if (tid == 0) {
       ProbeRec *h = hist_of(P, sig) + level;
       h->B = (int32_t)B;
@@ -1675,18 +1697,20 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
       h->T = Td;
       if ((int32_t)level != P.probe_drop)
         __hip_atomic_store(&h->k, (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // the last of the round's workgroups of this signal applies the rule;
-      // it reads only the counts, themselves atomics, so no fence (an
-      // agent-scope fence writes back and invalidates the L2).  A signal has
-      // as many workgroups in the round as it has levels in it (a shorter
-      // signal of an uneven batch may have fewer levels than the launch).
-      const uint32_t in_round = min((uint32_t)iter + gridDim.x, P.probe_levels) - (uint32_t)iter;
       const uint32_t prior = __hip_atomic_fetch_add(&st->round_blocks, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-      if (prior + 1u == in_round) {
-        __hip_atomic_store(&st->round_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        probe_control<NDIM>(P, sig, iter, iter + (int)in_round);
-      }
+      last = prior + 1u == in_round ? 1u : 0u;
+      if (last) __hip_atomic_store(&st->round_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (__builtin_amdgcn_readfirstlane(last)) {
+      // wave 0 reads the round's counts together, a lane per level, into
+      // LDS words the selects no longer use; lane 0 then applies the rule
+      int32_t *kv = reinterpret_cast<int32_t *>(hist);
+      if (tid < in_round) kv[tid] = probe_count(P, hist_of(P, sig) + iter + tid);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (tid == 0) probe_control<NDIM>(P, sig, iter, iter + (int)in_round, kv, st0);
     }
     return;
   }
@@ -2221,7 +2245,8 @@ __global__ __launch_bounds__(64) void k_bs_end(KParams P, int role, int iter) {
     h->T = bs->T;
     if ((int32_t)idx != P.probe_drop)
       __hip_atomic_store(&h->k, (int32_t)bs->nmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    probe_control<2>(P, sig, (int)idx, (int)idx + 1);
+    const int32_t kv = probe_count(P, h);
+    probe_control<2>(P, sig, (int)idx, (int)idx + 1, &kv, *state_of(P, sig));
     return;
   }
   tloc_of(P, sig)[idx] = bs->T;
