@@ -196,6 +196,9 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  *   ATSFFT_TILE_SLOTS    probe hash workgroups per slab and level, at most,
  *                        1..64 (32; at least 4 per compute unit over the batch)
  *   ATSFFT_PROBE_SLABS   1D probe levels: address slabs, 1 or 8 (1)
+ *   ATSFFT_ONE_SLAB_MAX_N  1D main-loop hash: lengths up to this power of two
+ *                        hashed as one address slab instead of 8 (2^21 when
+ *                        alpha <= 8, else none; 0: none)
  *   ATSFFT_VOTE_BLOCKS   vote workgroups per candidate loop (128 / batch, >= 32;
  *                        2D: 256 / batch, >= 64)
  *   ATSFFT_PROBE_FIRST   the first probe launch covers B up to this (2048)

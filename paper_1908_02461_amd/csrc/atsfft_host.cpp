@@ -31,6 +31,7 @@ struct atsfft_plan_s {
   size_t bucket_smem, est_smem, bwd_smem;
   uint32_t tile_slots;  // probe hash workgroups per slab and level, at most
   uint32_t main_slots;  // main-pass hash workgroups per slab and loop group
+  uint32_t one_slab_logn;  // 1D main pass: lengths up to 2^this hashed as one address slab
   uint32_t hash_loops;  // main-pass loops per hash workgroup
   uint32_t vote_blocks; // vote workgroups per (loop, signal)
   uint32_t rows2d_ok;   // 2D main loops may be hashed by rows staged in LDS
@@ -313,6 +314,8 @@ KParams make_params(const atsfft_plan_s *plan, const Layout &lay, const void *x_
   P.cut_ties = plan->cut_ties;
   P.tile_slots = plan->tile_slots;
   P.main_slots = plan->main_slots;
+  P.one_slab_logn = plan->one_slab_logn;
+  P.pad_kp = 0;
   P.hash_loops = plan->hash_loops;
   P.probe_levels = probe_levels(plan);
   for (uint32_t i = 0; i < (uint32_t)kMaxProbe; ++i)
@@ -498,6 +501,19 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
   // of 512 signals, most with few 64-bucket tiles, the idle slots cost more:
   // 6.87 ms per call with 32, 7.33 with 64)
   p->main_slots = 0;
+  // 1D main pass in one address slab where a lane has few wraps: at alpha = 8
+  // (two wraps per lane and loop) eight slabs leave most of its loads masked
+  // off.  Measured, batch 32, k = 64, hash us for 8 / 1 slabs: n = 2^18 alpha 8
+  // 174 / 98, alpha 32 210 / 258; n = 2^20 alpha 8 185 / 177, alpha 32 251 / 599;
+  // n = 2^21 alpha 8 177 / 195 (whole call 587 / 577: one partial per bucket
+  // for k_bucket); the uneven batch at alpha 8 is fastest with one slab up to
+  // 2^21 (5.01 ms per call, 6.46 with none, 5.14 up to 2^22).
+  p->one_slab_logn = d->ndim == 1 && d->alpha <= 8 ? 21u : 0u;
+  if (const char *env = std::getenv("ATSFFT_ONE_SLAB_MAX_N")) {
+    const long long v = std::strtoll(env, nullptr, 10);
+    if (v == 0) p->one_slab_logn = 0;
+    if (v >= 2 && (v & (v - 1)) == 0 && v <= (1LL << 30)) p->one_slab_logn = ilog2_host((uint64_t)v);
+  }
   if (const char *env = std::getenv("ATSFFT_MAIN_SLOTS")) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->main_slots = (uint32_t)v;

@@ -112,6 +112,8 @@ struct KParams {
   uint32_t est_wait;     // main k_bucket: estimation loops read their partials after the signal's
                          // location loops have (set for launches whose whole grid is resident)
   uint32_t cut_ties;     // test hook: location loops always take the tie-aware cutoff path
+  uint32_t one_slab_logn;  // 1D main-pass hash: signals of length at most 2^this as one address slab (0: none)
+  uint32_t pad_kp;
   uint32_t main_slots;   // main-pass hash: tile slots (workgroups) per slab and loop group (0: by batch)
   const void *G;       // window taps, plan precision
   const void *Ghat;    // G'(o) tables, plan precision

@@ -158,6 +158,23 @@ __device__ __forceinline__ uint32_t ilog2(uint32_t v) { return 31u - __clz(v); }
 // k_dev_setup wrote into the workspace.  A length outside the plan's range
 // reads the nearest covered one; k_init marks such a signal and every kernel
 // skips it.
+// log2 of a signal's length (DEV: clamped to the covered lengths, as
+// params_of picks them), without the per-length table.
+template <bool DEV> __device__ __forceinline__ uint32_t sig_logn(const KParams &P, uint32_t sig) {
+  if constexpr (DEV) {
+    const int64_t n = P.ns[sig];
+    const uint32_t lg = n > 0 ? 63u - (uint32_t)__clzll((unsigned long long)n) : 0u;
+    return min(max(lg, P.dev_lg_lo), P.dev_lg_hi);
+  } else {
+    return P.logn;
+  }
+}
+// Address slabs of a signal's 1D main-pass hash: one for lengths up to
+// 2^one_slab_logn, whose samples fit the caches whole, else kSlabs.
+template <bool DEV, int NDIM> __device__ __forceinline__ uint32_t main_slabs(const KParams &P, uint32_t sig) {
+  if (NDIM != 1 || P.one_slab_logn == 0u) return (uint32_t)kSlabs;
+  return sig_logn<DEV>(P, sig) <= P.one_slab_logn ? 1u : (uint32_t)kSlabs;
+}
 template <bool DEV> __device__ __forceinline__ const KParams &params_of(const KParams &P, uint32_t sig) {
   if constexpr (DEV) {
     const int64_t n = P.ns[sig];
@@ -611,13 +628,23 @@ template <typename R, int NDIM, int LG, bool COMP = false, bool MAIN = true, boo
 __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter, int iter_hi) {
   using C = typename CT<R>::C;
   const uint32_t sig = blockIdx.z;
-  const KParams &P = params_of<DEV>(P0, sig);
+  // the control block's address needs no per-length parameters (every
+  // length of a device-length launch shares the slice layout): it is read
+  // first, and a main-pass workgroup with no tile of its signal's B leaves
+  // before the per-length parameters are read
+  const SigState st = *state_of(P0, sig);  // one 64-byte read
+  const uint32_t NSm = MAIN ? main_slabs<DEV, NDIM>(P0, sig) : 1u;
+  if constexpr (MAIN) {
+    if ((st.status & kSigEmpty) || st.pass != (int32_t)P0.pass) return;
+    const uint32_t Bs = (uint32_t)st.B_star;
+    if ((blockIdx.x / NSm) * kTile >= (NDIM == 1 ? Bs : Bs * Bs)) return;
+  }
   constexpr bool main_phase = MAIN;
   static_assert(NDIM == 1 || LG == 1, "2D hashes one loop per workgroup");
   // 2D probe levels read few rows more than once: one slab, no row filter;
   // 1D probe levels as the plan says (their lines are cold and rarely
   // touched twice, so one slab spares the other workgroups' address scans)
-  const uint32_t NS = MAIN ? (uint32_t)kSlabs : NDIM == 1 ? P.probe_slabs : 1u;
+  const uint32_t NS = MAIN ? NSm : NDIM == 1 ? P0.probe_slabs : 1u;
   const uint32_t slab = blockIdx.x % NS;
   uint32_t slot = blockIdx.x / NS;
   uint32_t nslots = gridDim.x / NS;
@@ -634,8 +661,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(KParams P0, int iter, int
       slot -= nslots;
       ++level;
     }
+    if (slot >= nslots || st.done) return;
   }
-  const SigState st = *state_of(P, sig);  // one 64-byte read
+  const KParams &P = params_of<DEV>(P0, sig);
   uint32_t B, alpha, nl = 1;
   Draw d0[LG], d1[LG];
   C *y[LG];
@@ -1370,15 +1398,23 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
     loop = i < nloc ? i / batch : P0.L_loc + (i - nloc) / batch;
     sig = (i < nloc ? i : i - nloc) % batch;
   }
-  const KParams &P = params_of<DEV>(P0, sig);
   const uint32_t level = (uint32_t)iter + blockIdx.x;
-  SigState *st = state_of(P, sig);
-  uint32_t B;
-  C *yg;
+  SigState *st = state_of(P0, sig);  // the slice layout is every length's (see k_hash)
+  if (main_phase) {
+    if ((st->status & kSigEmpty) || st->pass != (int32_t)P0.pass) return;
+    const uint32_t Bs = (uint32_t)st->B_star, Bcs = NDIM == 1 ? Bs : Bs * Bs;
+    if ((main_phase == 3 && Bcs > kSmallBuckets) || (main_phase == 4 && Bcs <= kSmallBuckets)) return;
+  }
   SigState st0;  // probe role: the state as this round found it
   if (!main_phase) {
     st0 = *st;
-    if (st0.done || level >= P.probe_levels) return;
+    if (st0.done) return;
+  }
+  const KParams &P = params_of<DEV>(P0, sig);
+  uint32_t B;
+  C *yg;
+  if (!main_phase) {
+    if (level >= P.probe_levels) return;
     B = P.B0 << level;
     yg = yprobe_of<C>(P, sig, level);
   } else {
@@ -1431,7 +1467,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   const uint32_t nsl = !main_phase ? (NDIM == 1 ? P.probe_slabs : 1u)
                        : P.rows2d == 1 ? 1u
                        : P.rows2d == 2 ? (min(P.alpha * B, P.n) >> logB)
-                                       : (uint32_t)kSlabs;
+                                       : main_slabs<DEV, NDIM>(P0, sig);
   if constexpr (sizeof(R) == 4) {
     // c64: two neighbouring buckets per 16-byte load (bucket counts and slab
     // strides are even), two pairs per thread in flight; the same order of
@@ -2390,7 +2426,6 @@ constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x colu
 // not fit in LDS (the large 2D bucket arrays).
 template <int NDIM, bool SMALL, bool DEV = false, bool GB = false>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
-  const KParams &P = params_of<DEV>(P0, blockIdx.z);
   extern __shared__ uint32_t s_bits[];  // [L_loc][words]
   constexpr int K = kVoteIlp;
   constexpr uint32_t KB = kVoteBlock2d;
@@ -2400,14 +2435,16 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   __shared__ uint8_t s_qv[QCAP];
   __shared__ uint32_t s_qn;
   const uint32_t e = blockIdx.y, sig = blockIdx.z;
-  SigState *st = state_of(P, sig);
-  if ((st->status & kSigEmpty) || st->pass != (int32_t)P.pass) return;
+  // the control block and the cutoff counts have every length's slice layout,
+  // and the signal's length is its own: a workgroup with no work items leaves
+  // before the per-length parameters are read (see k_hash)
+  SigState *st = state_of(P0, sig);
+  if ((st->status & kSigEmpty) || st->pass != (int32_t)P0.pass) return;
   const int it0 = kPassIter * st->pass;
-  const uint32_t ncand = (uint32_t)jcount_of(P, sig)[e];
+  const uint32_t ncand = (uint32_t)jcount_of(P0, sig)[e];
   const uint32_t B = (uint32_t)st->B_star, logB = ilog2(B);
   const uint32_t Bc = NDIM == 1 ? B : B * B;
-  if ((Bc > P.lds_cap) != GB) return;  // bitmaps in LDS, or (GB) of the large arrays in device memory
-  const uint32_t n = P.n, mask = n - 1u, logn = P.logn;
+  const uint32_t logn = sig_logn<DEV>(P0, sig);
   const uint32_t logW = logn - logB, W = 1u << logW, c = W >> 1;
   // workgroup work items: selected buckets, or in 2D rounds of KB x KB blocks
   const bool blocks2 = NDIM == 2 && logW >= 2u;
@@ -2416,6 +2453,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(KParams P0) {
   const uint32_t items = blocks2 ? ((ncand << (2u * (logW - 2u))) + blockDim.x - 1u) / blockDim.x
                                  : ((ncand << logPer) + (uint32_t)K * blockDim.x - 1u) / ((uint32_t)K * blockDim.x);
   if (blockIdx.x >= items) return;
+  const KParams &P = params_of<DEV>(P0, sig);
+  if ((Bc > P.lds_cap) != GB) return;  // bitmaps in LDS, or (GB) of the large arrays in device memory
+  const uint32_t n = P.n, mask = n - 1u;
   const uint32_t L = P.L_loc, Tv = P.T_vote;
   const uint32_t words = (Bc + 31) >> 5;
   // tests before a candidate can fail; the slack of misses it may take

@@ -335,3 +335,17 @@ def test_main_hash_slots_leave_results_bitwise(A, monkeypatch, slots):
         assert np.array_equal(u["locs"], v["locs"]) and np.array_equal(u["vals"], v["vals"])
         tu, tv = ref_plan.trace(ref["ws"], i), plan.trace(out["ws"], i)
         assert np.array_equal(tu["yhat"], tv["yhat"])
+
+
+@pytest.mark.parametrize("one_slab", ["default", "0"])
+def test_filter_factor_8_slab_forms(A, monkeypatch, one_slab):
+    """At alpha = 8 the 1D main-loop hash of lengths up to 2^21 runs as one
+    address slab (one partial per bucket); with ATSFFT_ONE_SLAB_MAX_N=0 as
+    eight.  Both against the oracle, with a signal at 2^16 and one at 2^18."""
+    if one_slab != "default":
+        monkeypatch.setenv("ATSFFT_ONE_SLAB_MAX_N", one_slab)
+    for n, k in ((1 << 16, 20), (1 << 18, 90)):
+        plan = A.Plan(1, n, "c64", seed=41, max_batch=2, alpha=8, L_loc=7, L_est=7, T_vote=4, alpha_probe=8)
+        xs = [synth.planted_1d(n, k, 960 + i, mag=("uniform", 0.5, 1.0), snr_db=35.0, dtype=np.complex64)[0]
+              for i in range(2)]
+        _check_batch(A, plan, xs, f"alpha 8 n={n} one_slab={one_slab}")
