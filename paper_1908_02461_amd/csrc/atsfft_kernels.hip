@@ -3465,7 +3465,13 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       else
         hipLaunchKernelGGL((k_hash<R, NDIM, 1, false, false, DEV>), dim3(kProbeSlabs * slots, 1, batch),
                            dim3(kHashThreads), 0, s, Qp, (int)lo, (int)hi);
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(hi - lo, batch), dim3(kBucketThreads), bsmem, s, P, 0, (int)lo);
+      // a round whose grid is more than two workgroups per CU runs in
+      // 256-thread workgroups, several to a CU, when its levels allow (the
+      // workgroups of a small batch are latency chains, kept at 1024 threads)
+      const bool small_wg = (uint64_t)(hi - lo) * (uint64_t)batch > 2ull * P.n_cu && level_bc(hi - 1) <= kSmallBuckets;
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(hi - lo, batch),
+                         dim3(small_wg ? kSmallBucketThreads : kBucketThreads), small_wg ? bsmem_small : bsmem, s, P, 0,
+                         (int)lo);
       lo = hi;
     }
   }

@@ -349,3 +349,19 @@ def test_filter_factor_8_slab_forms(A, monkeypatch, one_slab):
         xs = [synth.planted_1d(n, k, 960 + i, mag=("uniform", 0.5, 1.0), snr_db=35.0, dtype=np.complex64)[0]
               for i in range(2)]
         _check_batch(A, plan, xs, f"alpha 8 n={n} one_slab={one_slab}")
+
+
+def test_probe_rounds_beyond_the_chip(A):
+    """80 signals of 2^16: the first probe round (seven levels, 32 to 2048
+    buckets) is a grid of 560 workgroups, more than two per CU, so it runs
+    in 256-thread workgroups; every probe count, decision and the rest
+    against the oracle."""
+    import torch
+
+    n = 1 << 16
+    ks = [4, 9, 17, 33, 60, 120, 200, 333] * 10
+    plan = A.Plan(1, n, "c64", seed=43, max_batch=len(ks))
+    assert 7 * len(ks) > 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    xs = [synth.planted_1d(n, k, 1200 + i, mag=("uniform", 0.5, 1.0), snr_db=30.0, dtype=np.complex64)[0]
+          for i, k in enumerate(ks)]
+    _check_batch(A, plan, xs, "probe rounds beyond the chip")
