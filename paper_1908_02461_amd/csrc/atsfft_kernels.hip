@@ -153,11 +153,6 @@ template <typename R> __device__ __forceinline__ const R *ghat_of(const KParams 
 
 __device__ __forceinline__ uint32_t ilog2(uint32_t v) { return 31u - __clz(v); }
 
-// The parameters signal `sig` runs with: the launch's own, or (DEV, an uneven
-// batch whose lengths are on the device) those of the signal's length, which
-// k_dev_setup wrote into the workspace.  A length outside the plan's range
-// reads the nearest covered one; k_init marks such a signal and every kernel
-// skips it.
 // log2 of a signal's length (DEV: clamped to the covered lengths, as
 // params_of picks them), without the per-length table.
 template <bool DEV> __device__ __forceinline__ uint32_t sig_logn(const KParams &P, uint32_t sig) {
@@ -169,21 +164,24 @@ template <bool DEV> __device__ __forceinline__ uint32_t sig_logn(const KParams &
     return P.logn;
   }
 }
+
 // Address slabs of a signal's 1D main-pass hash: one for lengths up to
-// 2^one_slab_logn, whose samples fit the caches whole, else kSlabs.
+// 2^one_slab_logn (plans whose lanes have few wraps each), else kSlabs.
 template <bool DEV, int NDIM> __device__ __forceinline__ uint32_t main_slabs(const KParams &P, uint32_t sig) {
   if (NDIM != 1 || P.one_slab_logn == 0u) return (uint32_t)kSlabs;
   return sig_logn<DEV>(P, sig) <= P.one_slab_logn ? 1u : (uint32_t)kSlabs;
 }
+
+// The parameters signal `sig` runs with: the launch's own, or (DEV, an uneven
+// batch whose lengths are on the device) those of the signal's length, which
+// k_dev_setup wrote into the workspace.  A length outside the plan's range
+// reads the nearest covered one; k_init marks such a signal and every kernel
+// skips it.
 template <bool DEV> __device__ __forceinline__ const KParams &params_of(const KParams &P, uint32_t sig) {
-  if constexpr (DEV) {
-    const int64_t n = P.ns[sig];
-    uint32_t lg = n > 0 ? 63u - (uint32_t)__clzll((unsigned long long)n) : 0u;
-    lg = min(max(lg, P.dev_lg_lo), P.dev_lg_hi);
-    return P.devP[lg];
-  } else {
+  if constexpr (DEV)
+    return P.devP[sig_logn<DEV>(P, sig)];
+  else
     return P;
-  }
 }
 __device__ __forceinline__ uint32_t bitrev(uint32_t v, uint32_t bits) {
   return bits ? (__brev(v) >> (32u - bits)) : 0u;
