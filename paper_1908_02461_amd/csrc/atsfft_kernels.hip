@@ -598,7 +598,7 @@ __global__ void k_init(KParams P0, int batch) {
 // the groups into the slab's partial y_b.  k_bucket adds the kSlabs partials
 // in slab order.
 constexpr int kTile = 64;        // buckets per tile
-constexpr int kVoteIlp = 4;      // vote candidates tested together (2, 4, 8: c2 vote 76, 64, 70 us)
+constexpr int kVoteIlp = 4;      // vote candidates tested together (2, 4, 8 at n = 2^22, batch 32: 76, 64, 70 us)
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
