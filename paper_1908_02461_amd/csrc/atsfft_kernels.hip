@@ -598,7 +598,7 @@ __global__ void k_init(KParams P0, int batch) {
 // the groups into the slab's partial y_b.  k_bucket adds the kSlabs partials
 // in slab order.
 constexpr int kTile = 64;        // buckets per tile
-constexpr int kVoteIlp = 4;      // vote candidates tested together (2, 4, 8 at n = 2^22, batch 32: 76, 64, 70 us)
+constexpr int kVoteIlp = 4;      // vote candidates tested together
 constexpr int kTileSlots = 64;   // most tile slots per slab (grid x = kSlabs * slots)
 constexpr int kHashU = 8;        // wraps whose loads are issued together
 
@@ -2412,7 +2412,8 @@ constexpr uint32_t kVoteBlock2d = 4;  // 2D vote: a thread's block of row x colu
 // index order, and after m tests with v hits it can still reach T_vote only
 // if v >= m - (L_loc - T_vote).  No candidate can fail before the first
 // L_loc - T_vote + 1 tests, so those run for every candidate without
-// branches, kVoteIlp candidates per thread; the few candidates still alive
+// branches, kVoteIlp candidates per thread (2, 4 and 8 measured at n = 2^22,
+// batch 32: 76, 64 and 70 us); the few candidates still alive
 // then go through an LDS queue, so that the remaining tests, which stop at
 // the first hopeless miss, run only on them.  In 2D a loop's bucket of (f1, f2)
 // is the pair of its bucket of f1 along rows and of f2 along columns, so a
