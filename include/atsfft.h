@@ -192,7 +192,7 @@ atsfft_status atsfft_default_desc(atsfft_desc *d, int32_t ndim, int64_t n, int32
  * them changes a result beyond the order of floating-point sums):
  *   ATSFFT_HASH_LOOPS    1D main loops per hash workgroup, 1..3 (3)
  *   ATSFFT_MAIN_SLOTS    main-loop hash workgroups per address slab and loop
- *                        group, 1..64 (64 for batches up to 32 signals, else 32)
+ *                        group, 1..64 (64 for batches up to 64 signals, else 32)
  *   ATSFFT_TILE_SLOTS    probe hash workgroups per slab and level, at most,
  *                        1..64 (32; at least 4 per compute unit over the batch)
  *   ATSFFT_PROBE_SLABS   1D probe levels: address slabs, 1 or 8 (1)

@@ -496,10 +496,11 @@ static atsfft_status create_plan(atsfft_plan_t *out, const atsfft_desc *d) {
     const long v = std::strtol(env, nullptr, 10);
     if (v >= 1 && v <= 64) p->tile_slots = (uint32_t)v;
   }
-  // 0: by batch, 64 slots up to 32 signals, else 32 (measured at n = 2^22, batch
-  // 32, B* 2048 and 4096: 32, 48, 64 slots 420, 416, 413 us; on the uneven batch
-  // of 512 signals, most with few 64-bucket tiles, the idle slots cost more:
-  // 6.87 ms per call with 32, 7.33 with 64)
+  // 0: by batch, 64 slots up to 64 signals, else 32 (measured at n = 2^22, batch
+  // 32, B* 2048 and 4096: 32, 48, 64 slots 420, 416, 413 us; batch 64: 822 and
+  // 807 us for 32 and 64; n = 2^20, batch 64 forward + adjoint: 2.381 and 2.331
+  // ms per step; on the uneven batch of 512 signals, most with few 64-bucket
+  // tiles, the idle slots cost more: 6.87 ms per call with 32, 7.33 with 64)
   p->main_slots = 0;
   // 1D main pass in one address slab where a lane has few wraps: at alpha = 8
   // (two wraps per lane and loop) eight slabs leave most of its loads masked

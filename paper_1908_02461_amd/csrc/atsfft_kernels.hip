@@ -3413,7 +3413,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   // the main k_bucket launches, one per class of array that can occur
   const uint64_t bc_min = NDIM == 1 ? (uint64_t)P.B0 : (uint64_t)P.B0 * P.B0;
   const size_t esmem = estimate_smem_bytes(P.max_out);
-  const uint32_t main_slots = P.main_slots ? P.main_slots : batch <= 32 ? 64u : 32u;
+  const uint32_t main_slots = P.main_slots ? P.main_slots : batch <= 64 ? 64u : 32u;
   const uint32_t hash_blocks = kSlabs * max(1u, min(main_slots, (P.Bc_max + kTile - 1) / kTile));
   if (mark) mark(ctx, 0);
   hipLaunchKernelGGL(k_init<DEV>, dim3((batch + 255) / 256), dim3(256), 0, s, P, batch);
