@@ -3494,9 +3494,14 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
   const bool rows = !DEV && NDIM == 2 && P.rows2d_ok && !P.x_off && (reinterpret_cast<uintptr_t>(P.x) & 15u) == 0 && !P.comp;
   const uint32_t row_mode = rows ? P.rows2d_ok : 0u;  // 1: per bucket row, 2: streamed
   // when the grid exceeds the chip (one 1024-thread workgroup per CU) the
-  // small arrays take 256-thread workgroups, several to a CU; otherwise
-  // every array a 1024-thread one (a chain of four waves is the longer)
+  // small arrays take 256-thread workgroups, several to a CU, or 512-thread
+  // ones while there are at most four arrays per CU (n = 2^22, batch 32: 48 ->
+  // 44 us; 512 signals of 2^16..2^22: 4.88 -> 4.96 ms per call with 512
+  // threads throughout); otherwise every array a 1024-thread one (a chain of
+  // four waves is the longer)
   const bool split = (uint64_t)loops * (uint64_t)batch > (uint64_t)P.n_cu;
+  const uint32_t small_threads =
+      (uint64_t)loops * (uint64_t)batch <= 4ull * P.n_cu ? 2u * (uint32_t)kSmallBucketThreads : (uint32_t)kSmallBucketThreads;
   const bool small_main = (P.fixed ? (uint64_t)P.Bc_max : bc_min) <= kSmallBuckets;
   const bool large_main = min(P.Bc_max, P.lds_cap) > kSmallBuckets;
   auto launch_main_bucket = [&](const KParams &Q) {
@@ -3505,8 +3510,7 @@ static hipError_t run(const KParams &P, int batch, hipStream_t s, StageMark mark
       return;
     }
     if (small_main)
-      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kSmallBucketThreads), bsmem_small, s, Q,
-                         3, 0);
+      hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(small_threads), bsmem_small, s, Q, 3, 0);
     if (large_main)
       hipLaunchKernelGGL((k_bucket<R, NDIM, DEV>), dim3(loops * batch), dim3(kBucketThreads), bsmem, s, Q, 4, 0);
   };
