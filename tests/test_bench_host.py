@@ -30,3 +30,26 @@ def test_oracle_agreement_uses_the_floor_denominator():
 
 def test_cpu_model_is_named():
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_traffic_summary_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
+    """The committed HBM-traffic summary is reported only while the k_hash
+    source section, the lines that size its grid and the batch are the ones
+    the counters were taken on."""
+    p = tmp_path / "traffic.txt"
+
+    def write(src_sha, launch_sha, batch=32):
+        p.write_text("# counters\nkernel = k_hash main loops\n"
+                     f"batch = {batch}\nhbm_bytes_per_launch = 123456\n"
+                     f"k_hash_source_sha256 = {src_sha}\nk_hash_launch_sha256 = {launch_sha}\n")
+
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    src, launch = bench.hash_kernel_sha256(), bench.hash_launch_sha256()
+    assert len(src) == 64 and len(launch) == 64 and src != launch
+    write(src, launch)
+    assert bench.measured_traffic(32) == 123456.0
+    assert bench.measured_traffic(64) is None  # another batch
+    write("0" * 64, launch)
+    assert bench.measured_traffic(32) is None  # the k_hash section changed
+    write(src, "0" * 64)
+    assert bench.measured_traffic(32) is None  # the grid sizing changed
