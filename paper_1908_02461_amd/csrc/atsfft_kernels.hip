@@ -1426,7 +1426,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket(KParams P0, int main_
   // a main pass whose grid exceeds the chip runs arrays of at most
   // kSmallBuckets in 256- or 512-thread workgroups, several to a CU, and the
   // larger ones in a launch of their own (phase 3: the small class, 4: the
-  // large); the class check is repeated here for the 2D arrays' own limit
+  // large); the same test as at the top, where it is made on the control block
   if ((main_phase == 3 && Bc > kSmallBuckets) || (main_phase == 4 && Bc <= kSmallBuckets)) return;
   const size_t sstride = main_phase ? (size_t)P.Bc_max : (size_t)Bc;  // between slab partials
   // what the statistics read from device memory, read before the bucket
